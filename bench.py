@@ -1,0 +1,268 @@
+"""Benchmark of the SU(3) link multiply c[s][j] = a[s][j] b[j] on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--L 48] [--forms f64,soa,f32,bf16,r12,copy,bwd]
+
+One step is one pass of the product over the whole lattice. The headline is
+the FP64 site-major (AoS) product on an L=48 lattice (5,308,416 sites, 3.06 GB
+per array): W untimed passes, then K passes timed with HIP events on the
+stream the kernel runs on, bracketed by device synchronisation. `value` is
+sites per second. The other storage forms, the SoA layout, the streaming copy
+over the same footprint (the measured bandwidth reference) and the adjoint
+(L=32) are timed the same way and reported under "forms".
+
+Inputs are seeded synthetic Haar SU(3) links (latgen), generated on the host
+and copied to HBM before timing starts. Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SU(3) link-mult sites/s & % HBM peak, L=48 FP64 vs FP32/recon-12"
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+FLOP_PER_SITE = 864            # paper's count: 4 x 27 x (4 mul + 4 add)
+# algorithmic bytes per site: a read once + c written once (b ignored)
+BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "f32": 576, "bf16": 288, "r12": 480}
+BWD_BYTES_PER_SITE = {"f64": 3 * 576, "f32": 3 * 288}   # a, dC read; dA written
+KERNEL_SOURCES = ["paper_2103_00571_amd/csrc/su3_fwd.hip", "paper_2103_00571_amd/csrc/su3_internal.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_aos_f64_L48.json")
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def time_launches(fn, steps: int, warmup: int, torch) -> float:
+    """Average milliseconds per call of fn() over `steps` back-to-back calls,
+    from HIP events on the current stream (where fn launches)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def traffic_record(bytes_alg: float):
+    """HBM traffic per launch of the FP64 AoS kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline_leg(a, b, sample_idx, seconds: float):
+    """The oracle (plain single-threaded C, FP64) timed on the host on a
+    bounded sample of the same workload, and its reference values on the
+    sampled sites used for the error report."""
+    import numpy as np
+
+    import oracle
+    O = oracle.default()
+    sample = np.ascontiguousarray(a[: 1 << 20])
+    O.mult_nn(sample[:1024], b)            # load and warm
+    passes, t0 = 0, time.perf_counter()
+    while True:
+        O.mult_nn(sample, b)
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    rate = passes * sample.shape[0] / el
+    ref = O.mult_nn(a[sample_idx], b)
+    rec = {"value": rate, "unit": "sites/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d sites of the L=48 lattice, FP64 AoS, %d passes in %.1f s, single thread"
+                     % (sample.shape[0], passes, el)}
+    return rec, ref, O
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--L", type=int, default=48)
+    ap.add_argument("--bwd-L", type=int, default=32)
+    ap.add_argument("--forms", default="f64,soa,f32,bf16,r12,copy,bwd")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
+              "(sites shard across GPUs with no communication in the forward pass); use --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import latgen
+    from paper_2103_00571_amd import ops
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    forms = [f for f in args.forms.split(",") if f]
+    L = args.L
+    sites = L ** 4
+
+    t0 = time.perf_counter()
+    a = latgen.random_lattice(sites, seed=1)
+    b = latgen.random_b(seed=2)
+    log("generated L=%d lattice (%d sites, %.2f GB) in %.1f s" % (L, sites, a.nbytes / 1e9, time.perf_counter() - t0))
+    ta = torch.from_numpy(a).to(dev)
+    tb64 = torch.from_numpy(b).to(dev)
+    tb32 = tb64.to(torch.complex64)
+    torch.cuda.synchronize()
+
+    results = {}
+    outputs = {}
+
+    def record(name, ms, nbytes_site, n_sites):
+        gbs = nbytes_site * n_sites / (ms * 1e-3) / 1e9
+        results[name] = {"ms": ms, "sites_per_s": n_sites / (ms * 1e-3), "gb_s": gbs,
+                         "frac_hbm_peak": gbs / HBM_PEAK_GBS, "gflop_s": FLOP_PER_SITE * n_sites / (ms * 1e-3) / 1e9}
+        log("%-5s %8.4f ms  %.3e sites/s  %7.1f GB/s  (%.1f%% of 8 TB/s)"
+            % (name, ms, n_sites / (ms * 1e-3), gbs, 100 * gbs / HBM_PEAK_GBS))
+
+    # ---- headline: FP64 AoS ------------------------------------------------
+    c64 = torch.empty_like(ta)
+    grid, block = ops.launch_shape(sites, ops.SU3_F64)
+    ms64 = time_launches(lambda: ops.mult_nn(ta, tb64, out=c64), args.steps, args.warmup, torch)
+    record("f64", ms64, BYTES_PER_SITE["f64"], sites)
+    outputs["f64"] = c64
+
+    # ---- streaming copy over the same footprint (measured bandwidth) -------
+    if "copy" in forms:
+        dst = torch.empty_like(ta)
+        msc = time_launches(lambda: ops.stream_copy(ta, dst), args.steps, args.warmup, torch)
+        msd = time_launches(lambda: dst.copy_(ta), max(10, args.steps // 4), 2, torch)
+        nb = 2 * a.nbytes
+        results["copy"] = {"ms": msc, "gb_s": nb / (msc * 1e-3) / 1e9, "bytes_moved": nb,
+                           "torch_copy_ms": msd, "torch_copy_gb_s": nb / (msd * 1e-3) / 1e9}
+        log("copy  %8.4f ms  %7.1f GB/s (library kernel); torch copy_ %7.1f GB/s"
+            % (msc, nb / (msc * 1e-3) / 1e9, nb / (msd * 1e-3) / 1e9))
+        del dst
+
+    # ---- SoA ---------------------------------------------------------------
+    if "soa" in forms:
+        sa = ops.aos_to_soa(ta)
+        sc = torch.empty_like(sa)
+        ms = time_launches(lambda: ops.mult_nn_soa(sa, tb64, out=sc), args.steps, args.warmup, torch)
+        record("soa", ms, BYTES_PER_SITE["soa"], sites)
+        outputs["soa"] = ops.soa_to_aos(sc)
+        del sa, sc
+
+    # ---- reduced storage forms -----------------------------------------------
+    for name, code in (("f32", ops.SU3_F32), ("bf16", ops.SU3_BF16), ("r12", ops.SU3_R12_F32)):
+        if name not in forms:
+            continue
+        x = ops.pack(ta, code)
+        y = ops.mult_nn(x, tb32)
+        ms = time_launches(lambda: ops.mult_nn(x, tb32, out=y), args.steps, args.warmup, torch)
+        record(name, ms, BYTES_PER_SITE[name], sites)
+        outputs[name] = y
+        del x
+    for name in ("f32", "bf16", "r12", "soa"):
+        if name in results:
+            results[name]["speedup_vs_f64"] = ms64 / results[name]["ms"]
+
+    # ---- adjoint (L = bwd-L) -----------------------------------------------
+    if "bwd" in forms:
+        bs = args.bwd_L ** 4
+        xa = torch.from_numpy(np.ascontiguousarray(a[:bs])).to(dev) if bs <= sites else None
+        if xa is not None:
+            xdc = torch.from_numpy(latgen.complex_normal_lattice(bs, seed=3)).to(dev)
+            for name, dt, tb in (("bwd_f64", torch.complex128, tb64), ("bwd_f32", torch.complex64, tb32)):
+                xa_, xdc_ = xa.to(dt), xdc.to(dt)
+                ms = time_launches(lambda: ops.mult_nn_bwd(xa_, tb, xdc_), args.steps, args.warmup, torch)
+                nb = BWD_BYTES_PER_SITE[name[4:]] * bs
+                results[name] = {"ms": ms, "sites_per_s": bs / (ms * 1e-3), "gb_s": nb / (ms * 1e-3) / 1e9,
+                                 "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "L": args.bwd_L}
+                log("%-7s %8.4f ms  %.3e sites/s  %7.1f GB/s" % (name, ms, bs / (ms * 1e-3), nb / (ms * 1e-3) / 1e9))
+            del xa, xdc
+
+    # ---- CPU baseline (oracle) and error report on sampled sites -------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        idx = np.unique(np.concatenate([np.random.default_rng(48).choice(sites, 4096, replace=False),
+                                        [0, sites - 1]]))
+        cpu, ref, O = cpu_baseline_leg(a, b, idx, args.cpu_seconds)
+        log("oracle on host: %.3e sites/s (%s)" % (cpu["value"], cpu["sample"]))
+        tidx = torch.from_numpy(idx).to(dev)
+        for name, out in outputs.items():
+            if name == "bf16":
+                got = O.widen_bf16(out[tidx].view(torch.int16).cpu().numpy().view(np.uint16))
+            else:
+                got = out[tidx].cpu().numpy().astype(np.complex128)
+            results[name]["max_abs_err_vs_oracle"] = O.max_abs_diff(got, ref)
+            results[name]["unitarity_dev"] = O.unitarity_dev(got)
+            results[name]["err_sample_sites"] = int(idx.size)
+
+    # ---- roofline of the dominant kernel ---------------------------------------
+    achieved = BYTES_PER_SITE["f64"] * sites / (ms64 * 1e-3) / 1e9
+    traffic = traffic_record(BYTES_PER_SITE["f64"] * sites)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "fwd_aos_f64", "bytes_per_launch": BYTES_PER_SITE["f64"] * sites,
+                "grid": grid, "block": block}
+    if "copy" in results:
+        roofline["frac_of_measured_copy"] = achieved / results["copy"]["gb_s"]
+
+    line = {
+        "metric": METRIC,
+        "value": results["f64"]["sites_per_s"],
+        "unit": "sites/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Haar SU(3) links, SplitMix64 + Box-Muller)",
+        "config": {"workload": "su3_mult_nn FP64 AoS, L=%d (%d sites, 4 links/site)" % (L, sites),
+                   "L": L, "sites": sites, "layout": "aos", "precision": "f64",
+                   "bytes_per_site": BYTES_PER_SITE["f64"], "flop_per_site": FLOP_PER_SITE},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": results,
+        "device": torch.cuda.get_device_name(dev),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

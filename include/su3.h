@@ -1,0 +1,178 @@
+/*
+ * su3.h -- C ABI of libsu3, the MI355X (gfx950) SU(3) link-multiply library.
+ *
+ * The operation is the core kernel of SU3_Bench (arXiv 2103.00571, section
+ * "Background", subsection SU3_Bench): over an L^4 lattice every site holds
+ * four links, each a 3x3 complex matrix, and for every site s and link j
+ *
+ *     c[s].link[j] = a[s].link[j] * b[j]          (j = 0..3)
+ *
+ * where each output entry (k, l) is the dot product of row k of a[s].link[j]
+ * with column l of b[j], and b is four matrices shared by every site.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named a, b, c, src, dst, dc, da are DEVICE pointers (memory the
+ *    caller allocated with hipMalloc or any allocator of device memory on the
+ *    current device). db_f64 is a device pointer too.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Every call is asynchronous on that stream: it only enqueues kernels and
+ *    returns. No call allocates memory, synchronises, or keeps pointers after
+ *    returning. The caller owns every buffer.
+ *  - `sites` is the number of lattice sites (L^4 for an L^4 lattice).
+ *    sites == 0 is valid and launches nothing.
+ *  - Complex numbers are interleaved (re, im). A link is row-major 3x3:
+ *    element (k, l) at complex offset 3k + l.
+ *  - Site-major ("AoS") layout: link j of site s at complex offset
+ *    (s*4 + j)*9; as a tensor, shape (sites, 4, 3, 3).
+ *  - Structure-of-arrays ("SoA") layout: 36 planes of `sites` complex
+ *    elements; element p = (j*3 + k)*3 + l of site s at complex offset
+ *    p*sites + s; as a tensor, shape (4, 3, 3, sites).
+ *  - Arguments are validated before anything is enqueued; on any error
+ *    nothing is launched and the status says why. A failed launch returns
+ *    SU3_ERR_HIP. Faults inside a kernel surface at the caller's next
+ *    synchronisation, as with any HIP library.
+ *  - Thread safety: calls may be made concurrently from several host threads.
+ *
+ * Storage forms (the `precision` argument)
+ * ----------------------------------------
+ *  code         a (per site)                b                 c (per site)
+ *  SU3_F64      4x3x3 complex double, 576 B  4x3x3 cdouble     576 B, FP64
+ *  SU3_F32      4x3x3 complex float,  288 B  4x3x3 cfloat      288 B, FP32
+ *  SU3_BF16     4x3x3x(re,im) bf16,   144 B  4x3x3 cfloat      144 B, BF16
+ *  SU3_R12_F32  rows 0-1 only: 4x2x3 cfloat, 4x3x3 cfloat      288 B, full FP32
+ *               192 B; row 2 is rebuilt as
+ *               conj(row0 x row1)
+ * FP32, BF16 and R12 compute in FP32; FP64 computes in FP64. BF16 results are
+ * rounded to nearest, ties to even. The reconstruct-12 form is valid for
+ * links in SU(3), for which the third row equals the conjugate cross product
+ * of the first two.
+ */
+#ifndef SU3_H
+#define SU3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SU3_ABI_VERSION 1
+
+/* storage form codes */
+enum su3_precision {
+    SU3_F64 = 0,
+    SU3_F32 = 1,
+    SU3_BF16 = 2,
+    SU3_R12_F32 = 3
+};
+
+/* status codes */
+enum su3_status {
+    SU3_OK = 0,
+    SU3_ERR_NULL = -1,       /* a required pointer is NULL while sites > 0     */
+    SU3_ERR_SIZE = -2,       /* sites < 0, or a byte count is out of range      */
+    SU3_ERR_ALIGN = -3,      /* a lattice pointer is not 16-byte aligned        */
+    SU3_ERR_PRECISION = -4,  /* unknown form, or a form this entry lacks        */
+    SU3_ERR_OVERLAP = -5,    /* an output overlaps an input                     */
+    SU3_ERR_WORKSPACE = -6,  /* workspace missing or smaller than required      */
+    SU3_ERR_HIP = -7         /* a HIP runtime call or kernel launch failed      */
+};
+
+/* Library version of this header; a mismatch means the .so is stale. */
+int su3_abi_version(void);
+
+/* Human-readable text of a status code (static string, never NULL). */
+const char *su3_status_string(int status);
+
+/*
+ * Forward product on the site-major layout (the paper's SU3_Bench kernel,
+ * section "Background", subsection SU3_Bench):
+ *   c[s][j](k, l) = sum_m a[s][j](k, m) * b[j](m, l).
+ * a, c: AoS arrays in the form `precision` (table above), 16-byte aligned,
+ * c must not overlap a or b (in-place is not supported). b: 4 links, in
+ * complex double for SU3_F64 and complex float for every other form; b needs
+ * only 8-byte alignment. c is overwritten, never accumulated.
+ * Errors: SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION,
+ * SU3_ERR_OVERLAP, SU3_ERR_HIP.
+ */
+int su3_mult_nn(const void *a, const void *b, void *c, int64_t sites,
+                int precision, void *stream);
+
+/*
+ * The same product on the SoA layout: a and c are 36 planes of `sites`
+ * complex elements. Supports SU3_F64 and SU3_F32 (other forms return
+ * SU3_ERR_PRECISION). Same alignment, overlap and error rules as
+ * su3_mult_nn.
+ */
+int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites,
+                    int precision, void *stream);
+
+/*
+ * Layout transforms between AoS and SoA for SU3_F64 and SU3_F32 (a pure
+ * permutation of complex elements, bit-exact). src and dst must not overlap
+ * and must be 16-byte aligned.
+ */
+int su3_aos_to_soa(const void *src, void *dst, int64_t sites, int precision,
+                   void *stream);
+int su3_soa_to_aos(const void *src, void *dst, int64_t sites, int precision,
+                   void *stream);
+
+/*
+ * Conversion from FP64 AoS links to a storage form, and back.
+ *  su3_pack:   src is FP64 AoS; dst is the `precision` form of a
+ *              (SU3_F32: round to nearest even; SU3_BF16: round to FP32, then
+ *              to BF16, each to nearest even; SU3_R12_F32: rows 0 and 1 of
+ *              every link rounded to FP32, 192 B per site; SU3_F64: copy).
+ *  su3_unpack: src is the `precision` form; dst is FP64 AoS. Widening is
+ *              exact; for SU3_R12_F32 row 2 is rebuilt in FP64 as
+ *              conj(row0 x row1) from the widened rows.
+ * Both are bit-exact functions of their input (integer-exact conversions).
+ */
+int su3_pack(const void *src_f64_aos, void *dst, int64_t sites, int precision,
+             void *stream);
+int su3_unpack(const void *src, void *dst_f64_aos, int64_t sites, int precision,
+               void *stream);
+
+/*
+ * Adjoint of su3_mult_nn for SU3_F64 and SU3_F32 (AoS). For the real loss
+ * Re sum conj(dc) * c, in the complex-gradient convention
+ * dL/dRe(x) + i dL/dIm(x):
+ *   da[s][j](k, m) = sum_l dc[s][j](k, l) * conj(b[j](m, l))      (dc b^H)
+ *   db[j](m, l)    = sum_s sum_k conj(a[s][j](k, m)) * dc[s][j](k, l)
+ * da has the form of a (FP64 or FP32). db_f64 receives 4x3x3 complex double
+ * (72 doubles) in every form: the site sum is accumulated in FP64 by a
+ * two-stage reduction whose order depends only on `sites`, so repeated calls
+ * give bit-identical db on any device. ws is device scratch of at least
+ * su3_mult_nn_bwd_workspace_bytes(sites, precision) bytes, 16-byte aligned,
+ * owned by the caller, contents undefined on entry and exit.
+ * da must not overlap a, b or dc; db_f64 and ws must not overlap anything.
+ * Errors: as su3_mult_nn, plus SU3_ERR_WORKSPACE.
+ */
+size_t su3_mult_nn_bwd_workspace_bytes(int64_t sites, int precision);
+int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da,
+                    double *db_f64, int64_t sites, int precision, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/*
+ * Measurement aid: device-to-device copy of `bytes` bytes with 16-byte
+ * loads and nontemporal 16-byte stores over a grid-stride loop, the same
+ * access pattern as the link multiply without the arithmetic. Used to
+ * measure the HBM bandwidth the multiply is compared against. bytes must be
+ * a multiple of 16; src and dst 16-byte aligned and non-overlapping.
+ */
+int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
+/*
+ * Launch shape the library uses for su3_mult_nn on the current device:
+ * writes the number of workgroups and threads per workgroup it would launch
+ * for (sites, precision). Returns SU3_OK or an error code.
+ */
+int su3_launch_shape(int64_t sites, int precision, int64_t *grid, int *block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SU3_H */

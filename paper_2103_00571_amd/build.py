@@ -1,0 +1,67 @@
+"""Build libsu3.so (the HIP kernels and the C ABI) for gfx950 in-tree.
+
+    python -m paper_2103_00571_amd.build [-D NAME=VALUE ...] [-o OUTPUT]
+
+Compiles every csrc/*.hip file with hipcc into one shared library placed next
+to this file, where the Python binding loads it from.
+"""
+
+from __future__ import annotations
+
+import argparse
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libsu3.so")
+ARCH = "gfx950"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "--offload-arch=" + ARCH,
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    "-Wall",
+    # no packed FP32 math: keep every FP32 operation a scalar VALU op
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def sources() -> list[str]:
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def build(output: str = LIB, defines: list[str] | None = None, verbose: bool = False) -> str:
+    """Compile the library; returns the output path. Raises on failure."""
+    cmd = [HIPCC, *FLAGS, *("-D" + d for d in (defines or [])), *sources(), "-o", output + ".tmp"]
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    # hipcc's host pass does not know the packed-fp32 target feature and says
+    # so; that line is expected and dropped.
+    noise = "is not a recognized feature for this target"
+    msgs = [l for l in (proc.stdout + proc.stderr).splitlines() if noise not in l]
+    if proc.returncode != 0:
+        raise RuntimeError("hipcc failed (%d):\n%s\n%s" % (proc.returncode, " ".join(cmd), "\n".join(msgs)))
+    if verbose and msgs:
+        print("\n".join(msgs), file=sys.stderr)
+    os.replace(output + ".tmp", output)
+    return output
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("-D", dest="defines", action="append", default=[], help="extra preprocessor definition")
+    ap.add_argument("-o", dest="output", default=LIB)
+    args = ap.parse_args()
+    print(build(args.output, args.defines, verbose=True))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,105 @@
+// su3_internal.hpp -- device helpers and launcher declarations shared by the
+// kernel files of libsu3 (gfx950). Not part of the public ABI (include/su3.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <tuple>
+
+namespace su3 {
+
+// 16-byte vector types as clang ext vectors, so that __builtin_nontemporal_*
+// accept them and the compiler emits one global_load/store_dwordx4 each.
+typedef double d2 __attribute__((ext_vector_type(2)));   // one complex double
+typedef float f4 __attribute__((ext_vector_type(4)));    // two complex float
+typedef float f2 __attribute__((ext_vector_type(2)));    // one complex float
+typedef uint32_t u4 __attribute__((ext_vector_type(4))); // eight bf16
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+// Streaming accesses: a and c are touched once per call, so loads and stores
+// carry the nontemporal hint (global_load/store ... nt) and do not displace
+// the b links or other data from the caches.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
+// complex multiply-accumulate acc += x * y, four fused multiply-adds
+__device__ __forceinline__ void cmac(double &re, double &im, double xr, double xi, double yr, double yi)
+{
+    re = __builtin_fma(xr, yr, re);
+    re = __builtin_fma(-xi, yi, re);
+    im = __builtin_fma(xr, yi, im);
+    im = __builtin_fma(xi, yr, im);
+}
+__device__ __forceinline__ void cmac(float &re, float &im, float xr, float xi, float yr, float yi)
+{
+    re = __builtin_fmaf(xr, yr, re);
+    re = __builtin_fmaf(-xi, yi, re);
+    im = __builtin_fmaf(xr, yi, im);
+    im = __builtin_fmaf(xi, yr, im);
+}
+
+// BF16 <-> FP32. Widening is a shift; narrowing rounds to nearest even
+// (v_cvt_pk_bf16_f32 on gfx950 under the default rounding mode).
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
+{
+    f2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2));
+}
+
+// Threads per workgroup of the streaming kernels: four wave64s.
+constexpr int kBlock = 256;
+
+// Devices per process for the per-device caches.
+constexpr int kMaxDevices = 64;
+
+// Launch a kernel through hipLaunchKernel, which reports a failed launch in
+// its return value; each argument is converted to the kernel's parameter type.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_k(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "argument count");
+    struct Pack {
+        std::tuple<KArgs...> t;
+    };
+    Pack p{std::tuple<KArgs...>(static_cast<KArgs>(args)...)};
+    void *argv[sizeof...(KArgs)];
+    std::apply([&](auto &...e) {
+        int i = 0;
+        ((argv[i++] = (void *)&e), ...);
+    }, p.t);
+    return hipLaunchKernel(reinterpret_cast<const void *>(k), grid, block, argv, 0, s);
+}
+
+// ---- launchers (each returns hipSuccess or the launch error) --------------
+// Forward, site-major layout. grid is a multiple of 3 so that the grid-stride
+// step keeps every thread on the same position inside a site.
+hipError_t launch_fwd_aos_f64(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
+hipError_t launch_fwd_aos_f32(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
+hipError_t launch_fwd_aos_bf16(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
+hipError_t launch_fwd_aos_r12(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
+// Workgroups of the forward kernel for `precision` (AoS) or of the SoA kernel
+// for `elem_bytes` that can be resident on one CU; <= 0 on a HIP error.
+int fwd_resident_blocks(int precision);
+int soa_resident_blocks(int elem_bytes);
+int copy_resident_blocks();
+// Forward, structure-of-arrays layout.
+hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, int64_t grid,
+                          hipStream_t s);
+// Layout and storage-form conversions.
+hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_bytes, bool to_soa, hipStream_t s);
+hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
+hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, int64_t grid, hipStream_t s);
+// Adjoint: stage 1 writes per-workgroup partial sums of db into ws, stage 2
+// reduces them in a fixed order.
+hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
+                      int precision, double *ws, int64_t groups, hipStream_t s);
+hipError_t launch_bwd_zero(double *db, hipStream_t s);
+
+} // namespace su3

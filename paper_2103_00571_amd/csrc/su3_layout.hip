@@ -1,0 +1,237 @@
+// su3_layout.hip -- data movement around the link multiply on gfx950:
+// AoS <-> SoA transposes, FP64 <-> storage-form conversion (pack/unpack),
+// and the plain streaming copy used as the bandwidth reference.
+#include "su3_internal.hpp"
+
+namespace su3 {
+
+// ------------------------------------------------------------ AoS <-> SoA
+// One workgroup moves a tile of 64 sites at a time through LDS: the site-
+// major side is read or written as one contiguous run of 64*36 elements, the
+// plane side as 36 contiguous runs of 64 elements. The LDS row has one
+// element of padding so that the column walk does not hit one bank.
+constexpr int kTileSites = 64;
+
+template <typename V, bool kToSoa>
+__global__ __launch_bounds__(kBlock) void transpose_aos_soa(const V *__restrict__ src, V *__restrict__ dst,
+                                                            int64_t n)
+{
+    __shared__ V tile[36][kTileSites + 1];
+    const int64_t tiles = (n + kTileSites - 1) / kTileSites;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t s0 = t * kTileSites;
+        const int ns = (int)((n - s0) < kTileSites ? (n - s0) : kTileSites);
+        if (kToSoa) {
+            for (int e = threadIdx.x; e < ns * 36; e += kBlock)
+                tile[e % 36][e / 36] = src[s0 * 36 + e];
+            __syncthreads();
+            for (int e = threadIdx.x; e < 36 * kTileSites; e += kBlock) {
+                const int p = e / kTileSites, sl = e % kTileSites;
+                if (sl < ns)
+                    dst[(int64_t)p * n + s0 + sl] = tile[p][sl];
+            }
+        } else {
+            for (int e = threadIdx.x; e < 36 * kTileSites; e += kBlock) {
+                const int p = e / kTileSites, sl = e % kTileSites;
+                if (sl < ns)
+                    tile[p][sl] = src[(int64_t)p * n + s0 + sl];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < ns * 36; e += kBlock)
+                dst[s0 * 36 + e] = tile[e % 36][e / 36];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ pack
+// FP64 complex -> FP32 complex, round to nearest even (v_cvt_f32_f64).
+__global__ __launch_bounds__(kBlock) void pack_f32(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const d2 v = src[e];
+        f2 o = {(float)v.x, (float)v.y};
+        dst[e] = o;
+    }
+}
+
+// FP64 complex -> BF16 (re, im), through FP32, each step to nearest even.
+__global__ __launch_bounds__(kBlock) void pack_bf16(const d2 *__restrict__ src, uint32_t *__restrict__ dst,
+                                                    int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const d2 v = src[e];
+        dst[e] = pack_bf16x2((float)v.x, (float)v.y);
+    }
+}
+
+// FP64 links -> rows 0 and 1 in FP32 (reconstruct-12 storage); thread per link.
+__global__ __launch_bounds__(kBlock) void pack_r12(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t links)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const d2 v = src[9 * t + q];
+            f2 o = {(float)v.x, (float)v.y};
+            dst[6 * t + q] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------ unpack
+__global__ __launch_bounds__(kBlock) void unpack_f32(const f2 *__restrict__ src, d2 *__restrict__ dst, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const f2 v = src[e];
+        d2 o = {(double)v.x, (double)v.y};
+        dst[e] = o;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void unpack_bf16(const uint32_t *__restrict__ src, d2 *__restrict__ dst,
+                                                      int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const uint32_t w = src[e];
+        d2 o = {(double)bf16_lo(w), (double)bf16_hi(w)};
+        dst[e] = o;
+    }
+}
+
+// Rows 0-1 in FP32 -> full FP64 link; row 2 = conj(row0 x row1) evaluated in
+// FP64 without contraction, each product and difference rounded on its own,
+// in the order (r0_p r1_q) - (r0_q r1_p) with each complex product formed as
+// (re*re - im*im, re*im + im*re). The result is then a fixed function of the
+// stored rows, independent of compiler contraction choices.
+__global__ __launch_bounds__(kBlock) void unpack_r12(const f2 *__restrict__ src, d2 *__restrict__ dst, int64_t links)
+{
+#pragma clang fp contract(off)
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
+        double r[12];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const f2 v = src[6 * t + q];
+            r[2 * q] = (double)v.x;
+            r[2 * q + 1] = (double)v.y;
+            d2 o = {r[2 * q], r[2 * q + 1]};
+            dst[9 * t + q] = o;
+        }
+        const double *r0 = r, *r1 = r + 6;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int p = (l + 1) % 3, q = (l + 2) % 3;
+            const double pr = r0[2 * p] * r1[2 * q] - r0[2 * p + 1] * r1[2 * q + 1];
+            const double pi = r0[2 * p] * r1[2 * q + 1] + r0[2 * p + 1] * r1[2 * q];
+            const double qr = r0[2 * q] * r1[2 * p] - r0[2 * q + 1] * r1[2 * p + 1];
+            const double qi = r0[2 * q] * r1[2 * p + 1] + r0[2 * q + 1] * r1[2 * p];
+            d2 o = {pr - qr, -(pi - qi)};
+            dst[9 * t + 6 + l] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------ stream copy
+// c[i] = a[i] over 16-byte elements: nontemporal 16-byte loads and stores,
+// four elements in flight per thread per iteration.
+__global__ __launch_bounds__(kBlock) void stream_copy(const u4 *__restrict__ src, u4 *__restrict__ dst, int64_t n)
+{
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * step < n; i += 4 * step) {
+        const u4 v0 = ld_stream(src + i);
+        const u4 v1 = ld_stream(src + i + step);
+        const u4 v2 = ld_stream(src + i + 2 * step);
+        const u4 v3 = ld_stream(src + i + 3 * step);
+        st_stream(dst + i, v0);
+        st_stream(dst + i + step, v1);
+        st_stream(dst + i + 2 * step, v2);
+        st_stream(dst + i + 3 * step, v3);
+    }
+    for (; i < n; i += step)
+        st_stream(dst + i, ld_stream(src + i));
+}
+
+// ------------------------------------------------------------ launchers
+static unsigned grid_for(int64_t items, int64_t per_block)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g > 65536)
+        g = 65536;
+    if (g < 1)
+        g = 1;
+    return (unsigned)g;
+}
+
+hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_bytes, bool to_soa, hipStream_t s)
+{
+    const unsigned g = grid_for(sites, kTileSites);
+    if (elem_bytes == 16) {
+        if (to_soa)
+            return launch_k(transpose_aos_soa<d2, true>, dim3(g), dim3(kBlock), s, (const d2 *)src, (d2 *)dst, sites);
+        return launch_k(transpose_aos_soa<d2, false>, dim3(g), dim3(kBlock), s, (const d2 *)src, (d2 *)dst, sites);
+    }
+    if (to_soa)
+        return launch_k(transpose_aos_soa<f2, true>, dim3(g), dim3(kBlock), s, (const f2 *)src, (f2 *)dst, sites);
+    return launch_k(transpose_aos_soa<f2, false>, dim3(g), dim3(kBlock), s, (const f2 *)src, (f2 *)dst, sites);
+}
+
+int copy_resident_blocks()
+{
+    static std::atomic<int> cache[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return -1;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0)
+        return n;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(stream_copy), kBlock, 0) !=
+            hipSuccess ||
+        n <= 0)
+        return -1;
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, int64_t grid, hipStream_t s)
+{
+    return launch_k(stream_copy, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)src, (u4 *)dst, bytes / 16);
+}
+
+// precision codes as in su3.h: 0 F64, 1 F32, 2 BF16, 3 R12_F32
+hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s)
+{
+    const int64_t elems = sites * 36, links = sites * 4;
+    switch (precision) {
+    case 1:
+        return launch_k(pack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const d2 *)src, (f2 *)dst, elems);
+    case 2:
+        return launch_k(pack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const d2 *)src,
+                        (uint32_t *)dst, elems);
+    case 3:
+        return launch_k(pack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, (const d2 *)src, (f2 *)dst, links);
+    default:
+        return launch_k(stream_copy, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const u4 *)src, (u4 *)dst,
+                        elems);
+    }
+}
+
+hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s)
+{
+    const int64_t elems = sites * 36, links = sites * 4;
+    switch (precision) {
+    case 1:
+        return launch_k(unpack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const f2 *)src, (d2 *)dst,
+                        elems);
+    case 2:
+        return launch_k(unpack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const uint32_t *)src,
+                        (d2 *)dst, elems);
+    case 3:
+        return launch_k(unpack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, (const f2 *)src, (d2 *)dst,
+                        links);
+    default:
+        return launch_k(stream_copy, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const u4 *)src, (u4 *)dst,
+                        elems);
+    }
+}
+
+} // namespace su3

@@ -1,0 +1,228 @@
+"""Torch-facing front end of libsu3: shape and dtype checks, output
+allocation with torch.empty, and the current HIP stream. PyTorch supplies
+device memory and streams only; every computation is a libsu3 kernel.
+
+Tensor forms (site-major "AoS", one row per site, see include/su3.h):
+
+    form          a                              b                  c
+    SU3_F64       complex128 (N, 4, 3, 3)        complex128 (4,3,3)  like a
+    SU3_F32       complex64  (N, 4, 3, 3)        complex64 (4,3,3)   like a
+    SU3_BF16      bfloat16   (N, 4, 3, 3, 2)     complex64 (4,3,3)   like a
+    SU3_R12_F32   complex64  (N, 4, 2, 3)        complex64 (4,3,3)   complex64 (N,4,3,3)
+
+SoA tensors are (4, 3, 3, N) in complex128 or complex64.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import abi
+from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, check
+
+__all__ = [
+    "SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32",
+    "form_of", "mult_nn", "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack",
+    "mult_nn_bwd", "stream_copy", "SU3MultNN", "mult_nn_autograd", "launch_shape",
+]
+
+_B_DTYPE = {SU3_F64: torch.complex128, SU3_F32: torch.complex64, SU3_BF16: torch.complex64,
+            SU3_R12_F32: torch.complex64}
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _need_gpu(*ts: torch.Tensor) -> None:
+    dev = ts[0].device
+    for t in ts:
+        if t.device.type != "cuda":
+            raise ValueError("libsu3 works on GPU tensors; got a tensor on %s" % t.device)
+        if t.device != dev:
+            raise ValueError("all tensors must be on one device")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def form_of(a: torch.Tensor) -> int:
+    """Storage form of an AoS lattice tensor, from its dtype and shape."""
+    if a.dtype == torch.complex128 and a.dim() == 4 and tuple(a.shape[1:]) == (4, 3, 3):
+        return SU3_F64
+    if a.dtype == torch.complex64 and a.dim() == 4 and tuple(a.shape[1:]) == (4, 3, 3):
+        return SU3_F32
+    if a.dtype == torch.bfloat16 and a.dim() == 5 and tuple(a.shape[1:]) == (4, 3, 3, 2):
+        return SU3_BF16
+    if a.dtype == torch.complex64 and a.dim() == 4 and tuple(a.shape[1:]) == (4, 2, 3):
+        return SU3_R12_F32
+    raise ValueError("not a lattice tensor: dtype %s shape %s" % (a.dtype, tuple(a.shape)))
+
+
+def _c_shape(form: int, sites: int) -> tuple:
+    return (sites, 4, 3, 3, 2) if form == SU3_BF16 else (sites, 4, 3, 3)
+
+
+def _c_dtype(form: int) -> torch.dtype:
+    return {SU3_F64: torch.complex128, SU3_F32: torch.complex64, SU3_BF16: torch.bfloat16,
+            SU3_R12_F32: torch.complex64}[form]
+
+
+def _check_b(b: torch.Tensor, form: int) -> None:
+    if b.dtype != _B_DTYPE[form] or tuple(b.shape) != (4, 3, 3):
+        raise ValueError("b must be %s of shape (4, 3, 3) for this form" % _B_DTYPE[form])
+
+
+def mult_nn(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """c[s][j] = a[s][j] @ b[j] on the site-major layout (any form)."""
+    form = form_of(a)
+    _check_b(b, form)
+    sites = a.shape[0]
+    if out is None:
+        out = torch.empty(_c_shape(form, sites), dtype=_c_dtype(form), device=a.device)
+    elif out.dtype != _c_dtype(form) or tuple(out.shape) != _c_shape(form, sites):
+        raise ValueError("out has the wrong dtype or shape")
+    _need_gpu(a, b, out)
+    with torch.cuda.device(a.device):
+        check(abi.su3_mult_nn(a.data_ptr(), b.data_ptr(), out.data_ptr(), sites, form, _stream(a)),
+              "su3_mult_nn")
+    return out
+
+
+def _soa_form(x: torch.Tensor) -> int:
+    if x.dim() == 4 and tuple(x.shape[:3]) == (4, 3, 3):
+        if x.dtype == torch.complex128:
+            return SU3_F64
+        if x.dtype == torch.complex64:
+            return SU3_F32
+    raise ValueError("not an SoA lattice tensor: dtype %s shape %s" % (x.dtype, tuple(x.shape)))
+
+
+def mult_nn_soa(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The same product on the SoA layout, (4, 3, 3, N) planes."""
+    form = _soa_form(a)
+    _check_b(b, form)
+    if out is None:
+        out = torch.empty_like(a)
+    elif out.dtype != a.dtype or out.shape != a.shape:
+        raise ValueError("out has the wrong dtype or shape")
+    _need_gpu(a, b, out)
+    with torch.cuda.device(a.device):
+        check(abi.su3_mult_nn_soa(a.data_ptr(), b.data_ptr(), out.data_ptr(), a.shape[3], form, _stream(a)),
+              "su3_mult_nn_soa")
+    return out
+
+
+def aos_to_soa(x: torch.Tensor) -> torch.Tensor:
+    form = form_of(x)
+    if form not in (SU3_F64, SU3_F32):
+        raise ValueError("SoA exists for FP64 and FP32 only")
+    out = torch.empty((4, 3, 3, x.shape[0]), dtype=x.dtype, device=x.device)
+    _need_gpu(x, out)
+    with torch.cuda.device(x.device):
+        check(abi.su3_aos_to_soa(x.data_ptr(), out.data_ptr(), x.shape[0], form, _stream(x)), "su3_aos_to_soa")
+    return out
+
+
+def soa_to_aos(x: torch.Tensor) -> torch.Tensor:
+    form = _soa_form(x)
+    out = torch.empty((x.shape[3], 4, 3, 3), dtype=x.dtype, device=x.device)
+    _need_gpu(x, out)
+    with torch.cuda.device(x.device):
+        check(abi.su3_soa_to_aos(x.data_ptr(), out.data_ptr(), x.shape[3], form, _stream(x)), "su3_soa_to_aos")
+    return out
+
+
+def _packed_spec(form: int, sites: int) -> tuple[tuple, torch.dtype]:
+    if form == SU3_F64:
+        return (sites, 4, 3, 3), torch.complex128
+    if form == SU3_F32:
+        return (sites, 4, 3, 3), torch.complex64
+    if form == SU3_BF16:
+        return (sites, 4, 3, 3, 2), torch.bfloat16
+    if form == SU3_R12_F32:
+        return (sites, 4, 2, 3), torch.complex64
+    raise ValueError("unknown form %r" % form)
+
+
+def pack(a64: torch.Tensor, form: int) -> torch.Tensor:
+    """FP64 AoS links -> storage form `form` (rounding to nearest even)."""
+    if form_of(a64) != SU3_F64:
+        raise ValueError("pack takes FP64 (complex128) links")
+    shape, dtype = _packed_spec(form, a64.shape[0])
+    out = torch.empty(shape, dtype=dtype, device=a64.device)
+    _need_gpu(a64, out)
+    with torch.cuda.device(a64.device):
+        check(abi.su3_pack(a64.data_ptr(), out.data_ptr(), a64.shape[0], form, _stream(a64)), "su3_pack")
+    return out
+
+
+def unpack(x: torch.Tensor, form: int | None = None) -> torch.Tensor:
+    """Storage form -> FP64 AoS links (R12 rebuilds row 2 in FP64)."""
+    form = form_of(x) if form is None else form
+    if form_of(x) != form:
+        raise ValueError("tensor is not in form %d" % form)
+    out = torch.empty((x.shape[0], 4, 3, 3), dtype=torch.complex128, device=x.device)
+    _need_gpu(x, out)
+    with torch.cuda.device(x.device):
+        check(abi.su3_unpack(x.data_ptr(), out.data_ptr(), x.shape[0], form, _stream(x)), "su3_unpack")
+    return out
+
+
+def mult_nn_bwd(a: torch.Tensor, b: torch.Tensor, dc: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:
+    """Adjoint: returns (da, db64) with da = dc b^H per site (dtype of a) and
+    db64 = sum_s a^H dc as complex128 (4, 3, 3), deterministic."""
+    form = form_of(a)
+    if form not in (SU3_F64, SU3_F32):
+        raise ValueError("the adjoint exists for FP64 and FP32")
+    _check_b(b, form)
+    if dc.dtype != a.dtype or dc.shape != a.shape:
+        raise ValueError("dc must match a in dtype and shape")
+    sites = a.shape[0]
+    da = torch.empty_like(a)
+    db = torch.empty((4, 3, 3), dtype=torch.complex128, device=a.device)
+    nbytes = abi.su3_mult_nn_bwd_workspace_bytes(sites, form)
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=a.device)
+    _need_gpu(a, b, dc, da, db, ws)
+    with torch.cuda.device(a.device):
+        check(abi.su3_mult_nn_bwd(a.data_ptr(), b.data_ptr(), dc.data_ptr(), da.data_ptr(), db.data_ptr(), sites,
+                                  form, ws.data_ptr(), ws.numel(), _stream(a)), "su3_mult_nn_bwd")
+    return da, db
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+    """dst <- src bytewise with the library's streaming copy kernel."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("size mismatch")
+    _need_gpu(src, dst)
+    with torch.cuda.device(src.device):
+        check(abi.su3_stream_copy(src.data_ptr(), dst.data_ptr(), n, _stream(src)), "su3_stream_copy")
+    return dst
+
+
+def launch_shape(sites: int, form: int, device: torch.device | int | None = None) -> tuple[int, int]:
+    """(workgroups, threads per workgroup) su3_mult_nn launches for this size."""
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        return abi.su3_launch_shape(sites, form)
+
+
+class SU3MultNN(torch.autograd.Function):
+    """c = a @ b[j] per site and link, differentiable in a and b (FP64, FP32).
+
+    backward uses the library's fused adjoint: da = dc b^H and a deterministic
+    FP64 site sum for db, returned in b's dtype."""
+
+    @staticmethod
+    def forward(ctx, a, b):
+        ctx.save_for_backward(a, b)
+        return mult_nn(a, b)
+
+    @staticmethod
+    def backward(ctx, dc):
+        a, b = ctx.saved_tensors
+        da, db = mult_nn_bwd(a, b, dc.contiguous())
+        return da, db.to(b.dtype)
+
+
+def mult_nn_autograd(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    return SU3MultNN.apply(a, b)

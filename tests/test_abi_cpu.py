@@ -1,0 +1,138 @@
+"""The C ABI on the CPU: libsu3.so loads, exports every function that
+include/su3.h declares, and rejects bad arguments before any HIP call (no
+pointer below is ever dereferenced; no GPU is needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "su3.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(su3_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2103_00571_amd import abi
+    return abi
+
+
+def test_header_matches_library_exports(abi):
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(abi.lib, n), "libsu3.so lacks %s" % n
+        assert n in abi.SIGNATURES, "binding lacks %s" % n
+        assert callable(getattr(abi, n)), "binding lacks a same-named wrapper for %s" % n
+    assert sorted(abi.SIGNATURES) == names
+
+
+def test_header_constants_match_binding(abi):
+    text = open(HEADER).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"\b(SU3_[A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    for k, v in consts.items():
+        assert getattr(abi, k) == v, k
+    assert int(re.search(r"#define SU3_ABI_VERSION (\d+)", text).group(1)) == abi.su3_abi_version()
+
+
+def test_status_strings(abi):
+    for code in range(0, -8, -1):
+        s = abi.su3_status_string(code)
+        assert s.startswith("SU3_")
+    assert "unknown" in abi.su3_status_string(42)
+
+
+A, B, C = 1 << 20, 1 << 30, 1 << 40   # 16-byte aligned fake device addresses, far apart
+
+
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
+def test_mult_nn_validation(abi, form):
+    f = abi.su3_mult_nn
+    assert f(A, B, C, 0, form, None) == abi.SU3_OK            # nothing to do: no launch
+    assert f(A, B, C, -1, form, None) == abi.SU3_ERR_SIZE
+    assert f(A, B, C, 1 << 62, form, None) == abi.SU3_ERR_SIZE
+    assert f(0, B, C, 5, form, None) == abi.SU3_ERR_NULL
+    assert f(A, 0, C, 5, form, None) == abi.SU3_ERR_NULL
+    assert f(A, B, 0, 5, form, None) == abi.SU3_ERR_NULL
+    assert f(A + 8, B, C, 5, form, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B, C + 4, 5, form, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B + 2, C, 5, form, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B, A, 5, form, None) == abi.SU3_ERR_OVERLAP            # in place
+    assert f(A, B, A + 16 * 7, 5, form, None) == abi.SU3_ERR_OVERLAP   # partial overlap
+    assert f(A, C + 32, C, 5, form, None) == abi.SU3_ERR_OVERLAP       # c covers b
+    assert f(A, B, C, 5, 4, None) == abi.SU3_ERR_PRECISION
+    assert f(A, B, C, 5, -1, None) == abi.SU3_ERR_PRECISION
+
+
+def test_soa_transform_pack_validation(abi):
+    for f in (abi.su3_mult_nn_soa,):
+        assert f(A, B, C, 5, 2, None) == abi.SU3_ERR_PRECISION
+        assert f(A, B, C, 5, 3, None) == abi.SU3_ERR_PRECISION
+        assert f(A, B, A, 5, 0, None) == abi.SU3_ERR_OVERLAP
+    for f in (abi.su3_aos_to_soa, abi.su3_soa_to_aos):
+        assert f(A, C, 0, 0, None) == abi.SU3_OK
+        assert f(A, C, 5, 2, None) == abi.SU3_ERR_PRECISION
+        assert f(A, A + 16, 5, 0, None) == abi.SU3_ERR_OVERLAP
+        assert f(A, C + 8, 5, 1, None) == abi.SU3_ERR_ALIGN
+        assert f(0, C, 5, 0, None) == abi.SU3_ERR_NULL
+    for f in (abi.su3_pack, abi.su3_unpack):
+        assert f(A, C, -3, 1, None) == abi.SU3_ERR_SIZE
+        assert f(A, C, 5, 7, None) == abi.SU3_ERR_PRECISION
+        assert f(A, A + 64, 5, 1, None) == abi.SU3_ERR_OVERLAP
+        assert f(A, 0, 5, 1, None) == abi.SU3_ERR_NULL
+
+
+def test_bwd_validation(abi):
+    ws_need = abi.su3_mult_nn_bwd_workspace_bytes(1000, 0)
+    assert ws_need > 0 and ws_need % 16 == 0
+    assert abi.su3_mult_nn_bwd_workspace_bytes(1000, 2) == 0
+    assert abi.su3_mult_nn_bwd_workspace_bytes(0, 0) == 0
+    # group count depends only on the site count, never on the device
+    assert abi.su3_mult_nn_bwd_workspace_bytes(10 ** 7, 0) == abi.su3_mult_nn_bwd_workspace_bytes(10 ** 7, 1)
+    D, DA, DB, WS = 1 << 41, 1 << 42, 1 << 43, 1 << 44
+    f = abi.su3_mult_nn_bwd
+    assert f(A, B, D, DA, DB, 1000, 2, WS, ws_need, None) == abi.SU3_ERR_PRECISION
+    assert f(A, B, D, DA, DB, 1000, 0, WS, ws_need - 8, None) == abi.SU3_ERR_WORKSPACE
+    assert f(A, B, D, DA, DB, 1000, 0, 0, ws_need, None) == abi.SU3_ERR_WORKSPACE
+    assert f(A, B, D, DA, 0, 1000, 0, WS, ws_need, None) == abi.SU3_ERR_NULL
+    assert f(A, B, D, A, DB, 1000, 0, WS, ws_need, None) == abi.SU3_ERR_OVERLAP
+    assert f(A, B, D, DA, DA + 64, 1000, 0, WS, ws_need, None) == abi.SU3_ERR_OVERLAP
+    assert f(A, B, D, DA, DB, 1000, 0, D, ws_need, None) == abi.SU3_ERR_OVERLAP
+    assert f(A, B, D, DA + 8, DB, 1000, 0, WS, ws_need, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B, D, DA, DB, -1, 0, WS, ws_need, None) == abi.SU3_ERR_SIZE
+
+
+def test_stream_copy_validation(abi):
+    assert abi.su3_stream_copy(A, C, 0, None) == abi.SU3_OK
+    assert abi.su3_stream_copy(A, C, 24, None) == abi.SU3_ERR_SIZE
+    assert abi.su3_stream_copy(A, A + 16, 64, None) == abi.SU3_ERR_OVERLAP
+    assert abi.su3_stream_copy(A + 4, C, 64, None) == abi.SU3_ERR_ALIGN
+
+
+def test_launch_shape_rejects_before_hip(abi):
+    g, b = ctypes.c_int64(), ctypes.c_int()
+    assert abi.lib.su3_launch_shape(10, 9, ctypes.byref(g), ctypes.byref(b)) == abi.SU3_ERR_PRECISION
+    assert abi.lib.su3_launch_shape(-1, 0, ctypes.byref(g), ctypes.byref(b)) == abi.SU3_ERR_SIZE
+    assert abi.lib.su3_launch_shape(10, 0, None, None) == abi.SU3_ERR_NULL
+
+
+def test_torch_front_end_rejects_cpu_and_bad_shapes():
+    import torch
+    from paper_2103_00571_amd import ops
+    a = torch.zeros((3, 4, 3, 3), dtype=torch.complex128)
+    b = torch.zeros((4, 3, 3), dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        ops.mult_nn(a, b)                       # CPU tensors: never computed on the host
+    with pytest.raises(ValueError):
+        ops.mult_nn(a, b.to(torch.complex64))   # b dtype must match the form
+    with pytest.raises(ValueError):
+        ops.form_of(torch.zeros((3, 4, 3, 2), dtype=torch.complex128))
+    assert ops.form_of(torch.zeros((3, 4, 2, 3), dtype=torch.complex64)) == ops.SU3_R12_F32
+    assert ops.form_of(torch.zeros((3, 4, 3, 3, 2), dtype=torch.bfloat16)) == ops.SU3_BF16
