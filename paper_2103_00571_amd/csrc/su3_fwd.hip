@@ -4,20 +4,18 @@
 // The product is HBM-bound (0.75 flop per byte in FP64), so the kernels are
 // built around the memory stream, not the arithmetic:
 //
-//  * Each thread owns a fixed "unit" position inside a site: the unit is the
-//    smallest run of output rows whose input and output bytes are whole,
-//    16-byte aligned multiples of 16 B (FP64: 1 row = 48 B in / 48 B out;
-//    FP32: 2 rows; BF16: 4 rows; reconstruct-12: 2 links = 96 B in / 144 B
-//    out). A wavefront therefore streams one contiguous span of memory with
-//    global_load/store_dwordx4, and every fetched cache line is used whole.
-//  * The grid is persistent (a multiple of 3 workgroups, a few per CU) and
-//    grid-strides over units. Because the step is a multiple of the number
-//    of units per site, a thread meets the same link index j on every
-//    iteration, so the b[j] entries it needs are loaded into registers once
-//    (the paper's "local transposed copy of B" on Xeon becomes registers).
-//  * Two units per iteration are loaded before either is stored, to keep
-//    more bytes in flight per wave.
-//  * Loads and stores of a and c are nontemporal (streamed once).
+//  * Site-major (AoS) forms: each thread owns a fixed "unit" position inside
+//    a site -- the smallest run of output rows whose input and output bytes
+//    are whole 16-byte chunks (FP64: 1 row, 48 B in / 48 B out; FP32: 2 rows;
+//    BF16: 4 rows; reconstruct-12: 2 links, 96 B in / 144 B out). Global
+//    memory is moved in whole-wavefront 1 KiB runs and transposed to one unit
+//    per lane through LDS (see fwd_aos).
+//  * The grid is persistent (every workgroup resident, a multiple of 3) and
+//    grid-strides over tiles. The stride is a whole number of sites, so a
+//    thread meets the same link index j on every tile and keeps the b[j]
+//    entries it needs in registers, loaded once (on Xeon the paper keeps a
+//    local transposed copy of B; here the copy is registers).
+//  * a and c are streamed with nontemporal 16-byte loads and stores.
 //  * 64-bit offsets throughout (a FP64 L=48 lattice is 3.06e9 bytes).
 #include "su3_internal.hpp"
 
@@ -27,71 +25,33 @@
 
 namespace su3 {
 
-// ---------------------------------------------------------------- FP64 AoS
-// unit = one output row (j, k) of one site: 3 complex doubles in and out.
-struct RowF64 {
-    d2 x[3];
-};
+// ------------------------------------------------------------ AoS forms
+// Each form describes one "unit" (kIn 16-byte chunks in, kOut chunks out,
+// kUnitsPerSite units per site), the b coefficients a thread at unit
+// position `pos` of a site needs, and the arithmetic of one unit.
 
-__device__ __forceinline__ void row_f64(const d2 *__restrict__ src, RowF64 &r)
-{
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-        r.x[m] = ld_stream(src + m);
-}
-
-__device__ __forceinline__ void row_f64_out(const RowF64 &r, const double (&br)[9], const double (&bi)[9],
-                                            d2 *__restrict__ dst)
+// three complex inputs x[0..5] (interleaved) times a 3x3 link -> one row
+template <typename S>
+__device__ __forceinline__ void row_times(const S *x, const S (&mr)[9], const S (&mi)[9], S *o)
 {
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        double re = 0.0, im = 0.0;
+        S re = 0, im = 0;
 #pragma unroll
         for (int m = 0; m < 3; ++m)
-            cmac(re, im, r.x[m].x, r.x[m].y, br[3 * m + l], bi[3 * m + l]);
-        d2 o = {re, im};
-        st_stream(dst + l, o);
+            cmac(re, im, x[2 * m], x[2 * m + 1], mr[3 * m + l], mi[3 * m + l]);
+        o[2 * l] = re;
+        o[2 * l + 1] = im;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fwd_aos_f64(const d2 *__restrict__ a, const double *__restrict__ b,
-                                                      d2 *__restrict__ c, int64_t rows)
-{
-    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    const int j = (int)((first % 12) / 3);
-    double br[9], bi[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        br[q] = b[2 * (9 * j + q)];
-        bi[q] = b[2 * (9 * j + q) + 1];
-    }
-    int64_t r = first;
-#if SU3_UNROLL >= 2
-    for (; r + step < rows; r += 2 * step) {
-        RowF64 u0, u1;
-        row_f64(a + 3 * r, u0);
-        row_f64(a + 3 * (r + step), u1);
-        row_f64_out(u0, br, bi, c + 3 * r);
-        row_f64_out(u1, br, bi, c + 3 * (r + step));
-    }
-#endif
-    for (; r < rows; r += step) {
-        RowF64 u0;
-        row_f64(a + 3 * r, u0);
-        row_f64_out(u0, br, bi, c + 3 * r);
-    }
-}
-
-// ---------------------------------------------------------------- FP32 AoS
-// unit = two consecutive output rows q0 = 2w, q0 + 1 of a site (w = 0..5),
-// 6 complex floats = 48 B = 3 x 16 B in and out. The rows may belong to two
-// different links (q / 3), so two b matrices are kept.
-struct BF32 {
-    float r[9], i[9];
+template <typename S>
+struct Link {
+    S r[9], i[9];
 };
 
-__device__ __forceinline__ void load_b_f32(const float *__restrict__ b, int j, BF32 &m)
+template <typename S>
+__device__ __forceinline__ void load_link(const S *__restrict__ b, int j, Link<S> &m)
 {
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -100,133 +60,108 @@ __device__ __forceinline__ void load_b_f32(const float *__restrict__ b, int j, B
     }
 }
 
-// one output row from three complex inputs (interleaved re/im in x[0..5])
-__device__ __forceinline__ void row_f32(const float *x, const BF32 &m, float *o)
+template <int N, typename S>
+__device__ __forceinline__ void unpack_chunks(const u4 (&v)[N], S *x)
 {
+    constexpr int P = 16 / sizeof(S);
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        float re = 0.0f, im = 0.0f;
+    for (int t = 0; t < N; ++t) {
+        typedef S SV __attribute__((ext_vector_type(P)));
+        const SV w = __builtin_bit_cast(SV, v[t]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            cmac(re, im, x[2 * k], x[2 * k + 1], m.r[3 * k + l], m.i[3 * k + l]);
-        o[2 * l] = re;
-        o[2 * l + 1] = im;
+        for (int h = 0; h < P; ++h)
+            x[P * t + h] = w[h];
     }
 }
 
-__device__ __forceinline__ void unit_f32(f4 *__restrict__ dst, const f4 (&v)[3], const BF32 &m0, const BF32 &m1)
+template <int N, typename S>
+__device__ __forceinline__ void pack_chunks(const S *x, u4 (&v)[N])
 {
-    float x[12], o[12];
+    constexpr int P = 16 / sizeof(S);
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        x[4 * t] = v[t].x;
-        x[4 * t + 1] = v[t].y;
-        x[4 * t + 2] = v[t].z;
-        x[4 * t + 3] = v[t].w;
-    }
-    row_f32(x, m0, o);
-    row_f32(x + 6, m1, o + 6);
+    for (int t = 0; t < N; ++t) {
+        typedef S SV __attribute__((ext_vector_type(P)));
+        SV w;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        f4 w = {o[4 * t], o[4 * t + 1], o[4 * t + 2], o[4 * t + 3]};
-        st_stream(dst + t, w);
+        for (int h = 0; h < P; ++h)
+            w[h] = x[P * t + h];
+        v[t] = __builtin_bit_cast(u4, w);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fwd_aos_f32(const f4 *__restrict__ a, const float *__restrict__ b,
-                                                      f4 *__restrict__ c, int64_t units)
-{
-    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    const int w = (int)(first % 6);
-    BF32 m0, m1;
-    load_b_f32(b, (2 * w) / 3, m0);
-    load_b_f32(b, (2 * w + 1) / 3, m1);
-    int64_t u = first;
-#if SU3_UNROLL >= 2
-    for (; u + step < units; u += 2 * step) {
-        f4 v0[3], v1[3];
+// FP64: unit = output row k of link j (pos = 3j + k); 48 B in, 48 B out.
+struct FormF64 {
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 12;
+    typedef double B;
+    typedef Link<double> Coef;
+    __device__ static void load(const B *b, int pos, Coef &m) { load_link(b, pos / 3, m); }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &m, u4 (&o)[kOut])
+    {
+        double x[6], y[6];
+        unpack_chunks<3>(v, x);
+        row_times(x, m.r, m.i, y);
+        pack_chunks<3>(y, o);
+    }
+};
+
+// FP32: unit = rows 2w and 2w+1 of a site (w = 0..5), which may belong to two
+// links; 48 B in, 48 B out.
+struct FormF32 {
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 6;
+    typedef float B;
+    struct Coef {
+        Link<float> m[2];
+    };
+    __device__ static void load(const B *b, int pos, Coef &c)
+    {
+        load_link(b, (2 * pos) / 3, c.m[0]);
+        load_link(b, (2 * pos + 1) / 3, c.m[1]);
+    }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &c, u4 (&o)[kOut])
+    {
+        float x[12], y[12];
+        unpack_chunks<3>(v, x);
+        row_times(x, c.m[0].r, c.m[0].i, y);
+        row_times(x + 6, c.m[1].r, c.m[1].i, y + 6);
+        pack_chunks<3>(y, o);
+    }
+};
+
+// BF16 storage, FP32 arithmetic: unit = rows 4w .. 4w+3 (w = 0..2); row i
+// uses link (4w + i) / 3; 48 B in, 48 B out, rounded to nearest even.
+struct FormBF16 {
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 3;
+    typedef float B;
+    struct Coef {
+        Link<float> m[4];
+    };
+    __device__ static void load(const B *b, int pos, Coef &c)
+    {
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            v0[t] = ld_stream(a + 3 * u + t);
-            v1[t] = ld_stream(a + 3 * (u + step) + t);
+        for (int i = 0; i < 4; ++i)
+            load_link(b, (4 * pos + i) / 3, c.m[i]);
+    }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &c, u4 (&o)[kOut])
+    {
+        uint32_t w[12];
+        unpack_chunks<3>(v, w);
+        float x[24], y[24];
+#pragma unroll
+        for (int h = 0; h < 12; ++h) {
+            x[2 * h] = bf16_lo(w[h]);
+            x[2 * h + 1] = bf16_hi(w[h]);
         }
-        unit_f32(c + 3 * u, v0, m0, m1);
-        unit_f32(c + 3 * (u + step), v1, m0, m1);
-    }
-#endif
-    for (; u < units; u += step) {
-        f4 v0[3];
 #pragma unroll
-        for (int t = 0; t < 3; ++t)
-            v0[t] = ld_stream(a + 3 * u + t);
-        unit_f32(c + 3 * u, v0, m0, m1);
+        for (int i = 0; i < 4; ++i)
+            row_times(x + 6 * i, c.m[i].r, c.m[i].i, y + 6 * i);
+#pragma unroll
+        for (int h = 0; h < 12; ++h)
+            w[h] = pack_bf16x2(y[2 * h], y[2 * h + 1]);
+        pack_chunks<3>(w, o);
     }
-}
+};
 
-// ---------------------------------------------------------------- BF16 AoS
-// unit = four consecutive output rows q = 4w .. 4w+3 (w = 0..2), 12 complex
-// bf16 = 48 B in and out. Row i uses b[(4w + i) / 3]; each row keeps its own
-// copy of the b entries it needs (selected once, outside the loop).
-__device__ __forceinline__ void unit_bf16(u4 *__restrict__ dst, const u4 (&v)[3], const BF32 (&m)[4])
-{
-    float x[24], o[24];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const uint32_t wv[4] = {v[t].x, v[t].y, v[t].z, v[t].w};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            x[8 * t + 2 * h] = bf16_lo(wv[h]);
-            x[8 * t + 2 * h + 1] = bf16_hi(wv[h]);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        row_f32(x + 6 * i, m[i], o + 6 * i);
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        u4 w = {pack_bf16x2(o[8 * t], o[8 * t + 1]), pack_bf16x2(o[8 * t + 2], o[8 * t + 3]),
-                pack_bf16x2(o[8 * t + 4], o[8 * t + 5]), pack_bf16x2(o[8 * t + 6], o[8 * t + 7])};
-        st_stream(dst + t, w);
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void fwd_aos_bf16(const u4 *__restrict__ a, const float *__restrict__ b,
-                                                       u4 *__restrict__ c, int64_t units)
-{
-    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    const int w = (int)(first % 3);
-    BF32 m[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        load_b_f32(b, (4 * w + i) / 3, m[i]);
-    int64_t u = first;
-#if SU3_UNROLL >= 2
-    for (; u + step < units; u += 2 * step) {
-        u4 v0[3], v1[3];
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            v0[t] = ld_stream(a + 3 * u + t);
-            v1[t] = ld_stream(a + 3 * (u + step) + t);
-        }
-        unit_bf16(c + 3 * u, v0, m);
-        unit_bf16(c + 3 * (u + step), v1, m);
-    }
-#endif
-    for (; u < units; u += step) {
-        u4 v0[3];
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-            v0[t] = ld_stream(a + 3 * u + t);
-        unit_bf16(c + 3 * u, v0, m);
-    }
-}
-
-// ----------------------------------------------------- reconstruct-12 AoS
-// unit = two links 2w, 2w+1 (w = 0, 1) of a site: rows 0-1 of each link in
-// FP32 (2 x 48 B = 6 x 16 B in), full 3x3 FP32 products out (2 x 72 B =
-// 9 x 16 B). Row 2 of each a link is rebuilt as conj(row0 x row1).
+// Third row of a link in SU(3) from its first two: conj(row0 x row1), FP32.
 __device__ __forceinline__ void recon_row2_f32(const float *r0, const float *r1, float *r2)
 {
 #pragma unroll
@@ -246,60 +181,115 @@ __device__ __forceinline__ void recon_row2_f32(const float *r0, const float *r1,
     }
 }
 
-__device__ __forceinline__ void unit_r12(f4 *__restrict__ dst, const f4 (&v)[6], const BF32 &m0, const BF32 &m1)
-{
-    float x[2][18], o[36];
+// Reconstruct-12: unit = links 2w, 2w+1 (w = 0, 1); rows 0-1 of each in FP32
+// (96 B in), the full FP32 products out (144 B).
+struct FormR12 {
+    static constexpr int kIn = 6, kOut = 9, kUnitsPerSite = 2;
+    typedef float B;
+    struct Coef {
+        Link<float> m[2];
+    };
+    __device__ static void load(const B *b, int pos, Coef &c)
+    {
+        load_link(b, 2 * pos, c.m[0]);
+        load_link(b, 2 * pos + 1, c.m[1]);
+    }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &c, u4 (&o)[kOut])
+    {
+        float x[24], y[36];
+        unpack_chunks<6>(v, x);   // link h: rows 0-1 at x[12h .. 12h+11]
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 2; ++h) {
+            float a[18];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            x[h][4 * t] = v[3 * h + t].x;
-            x[h][4 * t + 1] = v[3 * h + t].y;
-            x[h][4 * t + 2] = v[3 * h + t].z;
-            x[h][4 * t + 3] = v[3 * h + t].w;
+            for (int q = 0; q < 12; ++q)
+                a[q] = x[12 * h + q];
+            recon_row2_f32(a, a + 6, a + 12);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                row_times(a + 6 * k, c.m[h].r, c.m[h].i, y + 18 * h + 6 * k);
         }
-        recon_row2_f32(x[h], x[h] + 6, x[h] + 12);
+        pack_chunks<9>(y, o);
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        row_f32(x[0] + 6 * k, m0, o + 6 * k);
-        row_f32(x[1] + 6 * k, m1, o + 18 + 6 * k);
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        f4 w = {o[4 * t], o[4 * t + 1], o[4 * t + 2], o[4 * t + 3]};
-        st_stream(dst + t, w);
-    }
+};
+
+// Order LDS traffic between the lanes of one wavefront (LDS operations of a
+// wavefront execute in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(kBlock) void fwd_aos_r12(const f4 *__restrict__ a, const float *__restrict__ b,
-                                                      f4 *__restrict__ c, int64_t units)
+// Site-major forward for form F. A wavefront works on tiles of 64
+// consecutive units: its global loads and stores are whole 1 KiB runs (lane l
+// moves chunk i*64 + l of the tile), and a private LDS slice transposes
+// between that order and one unit per lane (lane l reads chunks
+// l*kIn .. l*kIn+kIn-1). No workgroup barrier is needed: each wavefront only
+// touches its own slice. kUnroll tiles are loaded before the first is
+// processed, to keep more bytes in flight.
+//
+// The tile stride (all wavefronts x 64 units) is a multiple of kUnitsPerSite
+// because the grid is a multiple of 3 workgroups of 256 threads, so lane l of
+// a wavefront sees the same unit position -- and the same b links -- on every
+// tile: its b coefficients are loaded once into registers.
+template <class F, int kUnroll>
+__global__ __launch_bounds__(kBlock) void fwd_aos(const u4 *__restrict__ a, const typename F::B *__restrict__ b,
+                                                  u4 *__restrict__ c, int64_t units)
 {
-    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    const int w = (int)(first % 2);
-    BF32 m0, m1;
-    load_b_f32(b, 2 * w, m0);
-    load_b_f32(b, 2 * w + 1, m1);
-    int64_t u = first;
-#if SU3_UNROLL >= 2
-    for (; u + step < units; u += 2 * step) {
-        f4 v0[6], v1[6];
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kSlots = 64 * (F::kIn > F::kOut ? F::kIn : F::kOut);
+    __shared__ u4 stage[kWaves][kSlots];
+    const int lane = threadIdx.x & 63;
+    u4 *my = stage[threadIdx.x >> 6];
+    const int64_t wave0 = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    typename F::Coef coef;
+    F::load(b, (int)((wave0 * 64 + lane) % F::kUnitsPerSite), coef);
+    const int64_t nin = units * F::kIn, nout = units * F::kOut;
+
+    for (int64_t t0 = wave0; t0 * 64 < units; t0 += kUnroll * nwaves) {
+        // all kUnroll tiles whole: no per-chunk bounds checks (wave-uniform)
+        const bool whole = (t0 + (kUnroll - 1) * nwaves + 1) * 64 <= units;
+        u4 v[kUnroll][F::kIn];
 #pragma unroll
-        for (int t = 0; t < 6; ++t) {
-            v0[t] = ld_stream(a + 6 * u + t);
-            v1[t] = ld_stream(a + 6 * (u + step) + t);
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t base = (t0 + u * nwaves) * 64 * F::kIn + lane;
+#pragma unroll
+            for (int i = 0; i < F::kIn; ++i) {
+                const int64_t g = base + 64 * i;
+                v[u][i] = (whole || g < nin) ? ld_stream(a + g) : u4{0, 0, 0, 0};
+            }
         }
-        unit_r12(c + 9 * u, v0, m0, m1);
-        unit_r12(c + 9 * (u + step), v1, m0, m1);
-    }
-#endif
-    for (; u < units; u += step) {
-        f4 v0[6];
 #pragma unroll
-        for (int t = 0; t < 6; ++t)
-            v0[t] = ld_stream(a + 6 * u + t);
-        unit_r12(c + 9 * u, v0, m0, m1);
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t t = t0 + u * nwaves;
+            if (t * 64 >= units)
+                break;
+#pragma unroll
+            for (int i = 0; i < F::kIn; ++i)
+                my[64 * i + lane] = v[u][i];
+            wave_sync();
+            u4 x[F::kIn], o[F::kOut];
+#pragma unroll
+            for (int i = 0; i < F::kIn; ++i)
+                x[i] = my[F::kIn * lane + i];
+            F::apply(x, coef, o);
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < F::kOut; ++i)
+                my[F::kOut * lane + i] = o[i];
+            wave_sync();
+            const int64_t base = t * 64 * F::kOut + lane;
+#pragma unroll
+            for (int i = 0; i < F::kOut; ++i) {
+                const int64_t g = base + 64 * i;
+                if (whole || g < nout)
+                    st_stream(c + g, my[64 * i + lane]);
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -361,10 +351,10 @@ int fwd_resident_blocks(int precision)
 {
     static std::atomic<int> c64[kMaxDevices], c32[kMaxDevices], c16[kMaxDevices], c12[kMaxDevices];
     switch (precision) {
-    case 0: return occupancy(reinterpret_cast<const void *>(fwd_aos_f64), c64);
-    case 1: return occupancy(reinterpret_cast<const void *>(fwd_aos_f32), c32);
-    case 2: return occupancy(reinterpret_cast<const void *>(fwd_aos_bf16), c16);
-    default: return occupancy(reinterpret_cast<const void *>(fwd_aos_r12), c12);
+    case 0: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormF64, SU3_UNROLL>), c64);
+    case 1: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormF32, SU3_UNROLL>), c32);
+    case 2: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormBF16, SU3_UNROLL>), c16);
+    default: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormR12, SU3_UNROLL>), c12);
     }
 }
 
@@ -378,26 +368,26 @@ int soa_resident_blocks(int elem_bytes)
 
 hipError_t launch_fwd_aos_f64(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
 {
-    return launch_k(fwd_aos_f64, dim3((unsigned)grid), dim3(kBlock), s, (const d2 *)a, (const double *)b, (d2 *)c,
-                    sites * 12);
+    return launch_k(fwd_aos<FormF64, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
+                    (const double *)b, (u4 *)c, sites * FormF64::kUnitsPerSite);
 }
 
 hipError_t launch_fwd_aos_f32(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
 {
-    return launch_k(fwd_aos_f32, dim3((unsigned)grid), dim3(kBlock), s, (const f4 *)a, (const float *)b, (f4 *)c,
-                    sites * 6);
+    return launch_k(fwd_aos<FormF32, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
+                    (const float *)b, (u4 *)c, sites * FormF32::kUnitsPerSite);
 }
 
 hipError_t launch_fwd_aos_bf16(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
 {
-    return launch_k(fwd_aos_bf16, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a, (const float *)b, (u4 *)c,
-                    sites * 3);
+    return launch_k(fwd_aos<FormBF16, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
+                    (const float *)b, (u4 *)c, sites * FormBF16::kUnitsPerSite);
 }
 
 hipError_t launch_fwd_aos_r12(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
 {
-    return launch_k(fwd_aos_r12, dim3((unsigned)grid), dim3(kBlock), s, (const f4 *)a, (const float *)b, (f4 *)c,
-                    sites * 2);
+    return launch_k(fwd_aos<FormR12, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
+                    (const float *)b, (u4 *)c, sites * FormR12::kUnitsPerSite);
 }
 
 hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, int64_t grid,
