@@ -3,13 +3,6 @@
 #include "../../include/su3.h"
 #include "su3_internal.hpp"
 
-#include <atomic>
-
-// Upper limit on resident workgroups per CU for the persistent kernels; the
-// occupancy calculator usually sets a lower one.
-#ifndef SU3_BLOCKS_PER_CU
-#define SU3_BLOCKS_PER_CU 16
-#endif
 
 namespace {
 
@@ -48,51 +41,11 @@ bool overlap(const void *p, int64_t pn, const void *q, int64_t qn)
 
 int status_of(hipError_t e) { return e == hipSuccess ? SU3_OK : SU3_ERR_HIP; }
 
-// compute units of the current device, cached per device
-std::atomic<int> g_cus[kMaxDevices];
+// A grid that covers the lattice once must stay below 2^32 work-items per
+// dimension (far beyond any lattice that fits in one GPU's memory).
+constexpr int64_t kMaxGridThreads = (int64_t)1 << 32;
 
-int device_cus(int *cus)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess)
-        return SU3_ERR_HIP;
-    if (dev < 0 || dev >= kMaxDevices)
-        return SU3_ERR_HIP;
-    int n = g_cus[dev].load(std::memory_order_relaxed);
-    if (n <= 0) {
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-            return SU3_ERR_HIP;
-        g_cus[dev].store(n, std::memory_order_relaxed);
-    }
-    *cus = n;
-    return SU3_OK;
-}
-
-// Persistent grid for the streaming kernels. Every workgroup must be resident
-// at once (a late wave of workgroups would double the tail), so the grid is
-// at most CUs x resident-workgroups-per-CU. It is a multiple of 3, so that the
-// grid-stride step is a whole number of sites for every form: rounded down
-// when capped by residency, rounded up (with idle workgroups) otherwise.
-int64_t persistent_grid(int64_t units, int cus, int resident)
-{
-    if (resident > SU3_BLOCKS_PER_CU)
-        resident = SU3_BLOCKS_PER_CU;
-    const int64_t need = (units + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)cus * resident;
-    if (need <= cap || cap < 3)
-        return need < 1 ? 3 : (need + 2) / 3 * 3;
-    return cap / 3 * 3;
-}
-
-int64_t units_per_site(int precision)
-{
-    switch (precision) {
-    case SU3_F64: return 12;
-    case SU3_F32: return 6;
-    case SU3_BF16: return 3;
-    default: return 2;
-    }
-}
+bool grid_fits(int64_t blocks, int64_t threads) { return blocks * threads < kMaxGridThreads; }
 
 // Adjoint stage-1 workgroups: a function of the site count only (never of the
 // device), capped, and a multiple of 3.
@@ -157,16 +110,9 @@ int su3_launch_shape(int64_t sites, int precision, int64_t *grid, int *block)
         return SU3_ERR_SIZE;
     if (!grid || !block)
         return SU3_ERR_NULL;
-    int cus = 0;
-    int st = device_cus(&cus);
-    if (st != SU3_OK)
-        return st;
-    const int res = fwd_resident_blocks(precision);
-    if (res <= 0)
-        return SU3_ERR_HIP;
-    *grid = sites == 0 ? 0 : persistent_grid(sites * units_per_site(precision), cus, res);
-    *block = kBlock;
-    return SU3_OK;
+    *grid = sites == 0 ? 0 : fwd_aos_grid(precision, sites);
+    *block = aos_block_threads();
+    return grid_fits(*grid, *block) ? SU3_OK : SU3_ERR_SIZE;
 }
 
 int su3_mult_nn(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
@@ -175,20 +121,9 @@ int su3_mult_nn(const void *a, const void *b, void *c, int64_t sites, int precis
     int st = check_lattice(a, b, c, sites, precision, f);
     if (st != SU3_OK || sites == 0)
         return st;
-    int cus = 0;
-    if ((st = device_cus(&cus)) != SU3_OK)
-        return st;
-    const int res = fwd_resident_blocks(precision);
-    if (res <= 0)
-        return SU3_ERR_HIP;
-    const int64_t grid = persistent_grid(sites * units_per_site(precision), cus, res);
-    hipStream_t s = (hipStream_t)stream;
-    switch (precision) {
-    case SU3_F64: return status_of(launch_fwd_aos_f64(a, b, c, sites, grid, s));
-    case SU3_F32: return status_of(launch_fwd_aos_f32(a, b, c, sites, grid, s));
-    case SU3_BF16: return status_of(launch_fwd_aos_bf16(a, b, c, sites, grid, s));
-    default: return status_of(launch_fwd_aos_r12(a, b, c, sites, grid, s));
-    }
+    if (!grid_fits(fwd_aos_grid(precision, sites), aos_block_threads()))
+        return SU3_ERR_SIZE;
+    return status_of(launch_fwd_aos(a, b, c, sites, precision, (hipStream_t)stream));
 }
 
 int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
@@ -199,21 +134,9 @@ int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites, int pr
     int st = check_lattice(a, b, c, sites, precision, f);
     if (st != SU3_OK || sites == 0)
         return st;
-    int cus = 0;
-    if ((st = device_cus(&cus)) != SU3_OK)
-        return st;
-    // four link rows (grid.y) of gx workgroups; all resident at once
-    const int eb = precision == SU3_F64 ? 16 : 8;
-    int res = soa_resident_blocks(eb);
-    if (res <= 0)
-        return SU3_ERR_HIP;
-    if (res > SU3_BLOCKS_PER_CU)
-        res = SU3_BLOCKS_PER_CU;
-    int64_t gx = (sites + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)cus * res / 4;
-    if (gx > cap)
-        gx = cap < 1 ? 1 : cap;
-    return status_of(launch_fwd_soa(a, b, c, sites, eb, gx, (hipStream_t)stream));
+    if (!grid_fits(fwd_soa_grid(sites), kBlock))
+        return SU3_ERR_SIZE;
+    return status_of(launch_fwd_soa(a, b, c, sites, precision == SU3_F64 ? 16 : 8, (hipStream_t)stream));
 }
 
 static int transform(const void *src, void *dst, int64_t sites, int precision, bool to_soa, void *stream)
@@ -260,6 +183,8 @@ static int convert(const void *src, void *dst, int64_t sites, int precision, boo
     const int64_t wide = sites * 576, narrow = sites * f.a_site;
     if (overlap(src, pack ? wide : narrow, dst, pack ? narrow : wide))
         return SU3_ERR_OVERLAP;
+    if (precision == SU3_F64 && !grid_fits(sites * 36, 1))
+        return SU3_ERR_SIZE;
     hipStream_t s = (hipStream_t)stream;
     return status_of(pack ? launch_pack(src, dst, sites, precision, s) : launch_unpack(src, dst, sites, precision, s));
 }
@@ -329,15 +254,9 @@ int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream)
         return SU3_ERR_ALIGN;
     if (overlap(src, bytes, dst, bytes))
         return SU3_ERR_OVERLAP;
-    int cus = 0;
-    int st = device_cus(&cus);
-    if (st != SU3_OK)
-        return st;
-    const int res = copy_resident_blocks();
-    if (res <= 0)
-        return SU3_ERR_HIP;
-    return status_of(
-        launch_stream_copy(src, dst, bytes, persistent_grid(bytes / 16, cus, res), (hipStream_t)stream));
+    if (!grid_fits(bytes / 16, 1))
+        return SU3_ERR_SIZE;
+    return status_of(launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
 }
 
 } // extern "C"

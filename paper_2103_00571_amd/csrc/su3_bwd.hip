@@ -127,21 +127,21 @@ hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, do
 {
     hipError_t e;
     if (precision == 0)
-        e = launch_k(bwd_rows<double>, dim3((unsigned)groups), dim3(kBlock), s, (const d2 *)a, (const double *)b,
+        e = launch_k(bwd_rows<double>, dim3((unsigned)groups), dim3(kBlock), s, 0, (const d2 *)a, (const double *)b,
                      (const d2 *)dc, (d2 *)da, ws, sites * 12);
     else
-        e = launch_k(bwd_rows<float>, dim3((unsigned)groups), dim3(kBlock), s, (const f2 *)a, (const float *)b,
+        e = launch_k(bwd_rows<float>, dim3((unsigned)groups), dim3(kBlock), s, 0, (const f2 *)a, (const float *)b,
                      (const f2 *)dc, (f2 *)da, ws, sites * 12);
     if (e != hipSuccess)
         return e;
-    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, (const double *)ws, db, groups);
+    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)ws, db, groups);
 }
 
 // An empty lattice has dB = 0: the second stage over zero partials writes
 // zeros (a kernel rather than a memset, so the call is safe to capture).
 hipError_t launch_bwd_zero(double *db, hipStream_t s)
 {
-    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, (const double *)nullptr, db, (int64_t)0);
+    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)nullptr, db, (int64_t)0);
 }
 
 } // namespace su3

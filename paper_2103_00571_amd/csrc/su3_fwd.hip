@@ -4,26 +4,55 @@
 // The product is HBM-bound (0.75 flop per byte in FP64), so the kernels are
 // built around the memory stream, not the arithmetic:
 //
-//  * Site-major (AoS) forms: each thread owns a fixed "unit" position inside
-//    a site -- the smallest run of output rows whose input and output bytes
-//    are whole 16-byte chunks (FP64: 1 row, 48 B in / 48 B out; FP32: 2 rows;
-//    BF16: 4 rows; reconstruct-12: 2 links, 96 B in / 144 B out). Global
-//    memory is moved in whole-wavefront 1 KiB runs and transposed to one unit
-//    per lane through LDS (see fwd_aos).
-//  * The grid is persistent (every workgroup resident, a multiple of 3) and
-//    grid-strides over tiles. The stride is a whole number of sites, so a
-//    thread meets the same link index j on every tile and keeps the b[j]
-//    entries it needs in registers, loaded once (on Xeon the paper keeps a
-//    local transposed copy of B; here the copy is registers).
+//  * Site-major (AoS) forms: a thread owns one "unit" -- the smallest run of
+//    output rows whose input and output bytes are whole 16-byte chunks (FP64:
+//    1 row, 48 B in / 48 B out; FP32: 2 rows; BF16: 4 rows; reconstruct-12:
+//    2 links, 96 B in / 144 B out). Global memory moves in whole-wavefront
+//    1 KiB runs and is transposed to one unit per lane through LDS (fwd_aos).
+//  * Structure-of-arrays: a thread owns one (site, output row); every plane
+//    access of a wavefront is already one contiguous run, and the row is
+//    uniform over a workgroup, so b[j] sits in scalar registers (fwd_soa).
+//  * The grid covers the lattice once: each wavefront streams one tile and
+//    exits, and the dispatcher hands out tiles in address order.
 //  * a and c are streamed with nontemporal 16-byte loads and stores.
 //  * 64-bit offsets throughout (a FP64 L=48 lattice is 3.06e9 bytes).
 #include "su3_internal.hpp"
 
-#ifndef SU3_UNROLL
-#define SU3_UNROLL 2
+// Threads per workgroup of the AoS kernels (a multiple of 64); each
+// wavefront of the workgroup handles its own tile.
+#ifndef SU3_AOS_BLOCK
+#define SU3_AOS_BLOCK 64
+#endif
+
+// Resident wavefronts per CU, per kernel. Fewer resident wavefronts mean
+// fewer bytes in flight; on MI355X the streaming rate of these kernels peaks
+// with about 33-36 KiB of loads in flight per CU (11-12 wavefronts of 3 KiB)
+// and falls steeply below about 9. Values from a sweep at L=48; 0 leaves
+// occupancy to the hardware.
+#ifndef SU3_WAVES_F64
+#define SU3_WAVES_F64 11
+#endif
+#ifndef SU3_WAVES_F32
+#define SU3_WAVES_F32 12
+#endif
+#ifndef SU3_WAVES_BF16
+#define SU3_WAVES_BF16 14
+#endif
+#ifndef SU3_WAVES_R12
+#define SU3_WAVES_R12 6
+#endif
+#ifndef SU3_WAVES_SOA_F64
+#define SU3_WAVES_SOA_F64 12
+#endif
+#ifndef SU3_WAVES_SOA_F32
+#define SU3_WAVES_SOA_F32 0
 #endif
 
 namespace su3 {
+
+constexpr int kAosBlock = SU3_AOS_BLOCK;
+
+int aos_block_threads() { return kAosBlock; }
 
 // ------------------------------------------------------------ AoS forms
 // Each form describes one "unit" (kIn 16-byte chunks in, kOut chunks out,
@@ -91,7 +120,7 @@ __device__ __forceinline__ void pack_chunks(const S *x, u4 (&v)[N])
 
 // FP64: unit = output row k of link j (pos = 3j + k); 48 B in, 48 B out.
 struct FormF64 {
-    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 12;
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 12, kWavesPerCU = SU3_WAVES_F64;
     typedef double B;
     typedef Link<double> Coef;
     __device__ static void load(const B *b, int pos, Coef &m) { load_link(b, pos / 3, m); }
@@ -107,7 +136,7 @@ struct FormF64 {
 // FP32: unit = rows 2w and 2w+1 of a site (w = 0..5), which may belong to two
 // links; 48 B in, 48 B out.
 struct FormF32 {
-    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 6;
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 6, kWavesPerCU = SU3_WAVES_F32;
     typedef float B;
     struct Coef {
         Link<float> m[2];
@@ -130,7 +159,7 @@ struct FormF32 {
 // BF16 storage, FP32 arithmetic: unit = rows 4w .. 4w+3 (w = 0..2); row i
 // uses link (4w + i) / 3; 48 B in, 48 B out, rounded to nearest even.
 struct FormBF16 {
-    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 3;
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 3, kWavesPerCU = SU3_WAVES_BF16;
     typedef float B;
     struct Coef {
         Link<float> m[4];
@@ -184,7 +213,7 @@ __device__ __forceinline__ void recon_row2_f32(const float *r0, const float *r1,
 // Reconstruct-12: unit = links 2w, 2w+1 (w = 0, 1); rows 0-1 of each in FP32
 // (96 B in), the full FP32 products out (144 B).
 struct FormR12 {
-    static constexpr int kIn = 6, kOut = 9, kUnitsPerSite = 2;
+    static constexpr int kIn = 6, kOut = 9, kUnitsPerSite = 2, kWavesPerCU = SU3_WAVES_R12;
     typedef float B;
     struct Coef {
         Link<float> m[2];
@@ -222,182 +251,205 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Site-major forward for form F. A wavefront works on tiles of 64
-// consecutive units: its global loads and stores are whole 1 KiB runs (lane l
-// moves chunk i*64 + l of the tile), and a private LDS slice transposes
-// between that order and one unit per lane (lane l reads chunks
-// l*kIn .. l*kIn+kIn-1). No workgroup barrier is needed: each wavefront only
-// touches its own slice. kUnroll tiles are loaded before the first is
-// processed, to keep more bytes in flight.
-//
-// The tile stride (all wavefronts x 64 units) is a multiple of kUnitsPerSite
-// because the grid is a multiple of 3 workgroups of 256 threads, so lane l of
-// a wavefront sees the same unit position -- and the same b links -- on every
-// tile: its b coefficients are loaded once into registers.
-template <class F, int kUnroll>
-__global__ __launch_bounds__(kBlock) void fwd_aos(const u4 *__restrict__ a, const typename F::B *__restrict__ b,
+// Site-major forward for form F. One wavefront handles one tile of 64
+// consecutive units and exits: its global loads and stores are whole 1 KiB
+// runs (lane l moves chunk i*64 + l of the tile), and a private LDS slice
+// transposes between that order and one unit per lane (lane l reads chunks
+// l*kIn .. l*kIn+kIn-1). The grid covers the lattice once, so the hardware
+// dispatcher issues tiles in address order; on MI355X this streams faster
+// than a persistent grid-stride loop (which lets workgroups drift apart in
+// memory). The four b links are staged once per workgroup in LDS and each
+// lane reads the coefficients of its own unit position from there.
+template <class F>
+__global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, const typename F::B *__restrict__ b,
                                                   u4 *__restrict__ c, int64_t units)
 {
-    constexpr int kWaves = kBlock / 64;
+    constexpr int kWaves = kAosBlock / 64;
     constexpr int kSlots = 64 * (F::kIn > F::kOut ? F::kIn : F::kOut);
     __shared__ u4 stage[kWaves][kSlots];
+    __shared__ __attribute__((aligned(16))) typename F::B bsh[72];
+
     const int lane = threadIdx.x & 63;
     u4 *my = stage[threadIdx.x >> 6];
-    const int64_t wave0 = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-    typename F::Coef coef;
-    F::load(b, (int)((wave0 * 64 + lane) % F::kUnitsPerSite), coef);
+    const int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const bool live = t * 64 < units;            // wave-uniform
+    const bool whole = (t + 1) * 64 <= units;    // wave-uniform (no ragged end)
     const int64_t nin = units * F::kIn, nout = units * F::kOut;
 
-    for (int64_t t0 = wave0; t0 * 64 < units; t0 += kUnroll * nwaves) {
-        // all kUnroll tiles whole: no per-chunk bounds checks (wave-uniform)
-        const bool whole = (t0 + (kUnroll - 1) * nwaves + 1) * 64 <= units;
-        u4 v[kUnroll][F::kIn];
+    // Load b (72 scalars, cached) first and the tile after it: vector memory
+    // operations retire in order, so the workgroup barrier that publishes b
+    // in LDS waits for the b load only while the tile is still in flight.
+    constexpr int kBPer = (72 + kAosBlock - 1) / kAosBlock;
+    typename F::B bv[kBPer];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t base = (t0 + u * nwaves) * 64 * F::kIn + lane;
+    for (int r = 0; r < kBPer; ++r) {
+        const int q = threadIdx.x + r * kAosBlock;
+        bv[r] = q < 72 ? b[q] : typename F::B(0);
+    }
+    // Branch-free tile loads: a chunk past the end of the lattice (ragged last
+    // tile, or a wavefront with no tile) re-reads the last chunk and is never
+    // used, so every load stays in bounds and the wait counts stay exact.
+    u4 v[F::kIn];
+    const int64_t gin = t * 64 * F::kIn + lane;
 #pragma unroll
-            for (int i = 0; i < F::kIn; ++i) {
-                const int64_t g = base + 64 * i;
-                v[u][i] = (whole || g < nin) ? ld_stream(a + g) : u4{0, 0, 0, 0};
-            }
-        }
+    for (int i = 0; i < F::kIn; ++i) {
+        const int64_t g = gin + 64 * i;
+        v[i] = ld_stream(a + (g < nin ? g : nin - 1));
+    }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t t = t0 + u * nwaves;
-            if (t * 64 >= units)
-                break;
+    for (int r = 0; r < kBPer; ++r) {
+        const int q = threadIdx.x + r * kAosBlock;
+        if (q < 72)
+            bsh[q] = bv[r];
+    }
+    __syncthreads();
+    if (!live)
+        return;
+    typename F::Coef coef;
+    F::load(bsh, (int)((t * 64 + lane) % F::kUnitsPerSite), coef);
 #pragma unroll
-            for (int i = 0; i < F::kIn; ++i)
-                my[64 * i + lane] = v[u][i];
-            wave_sync();
-            u4 x[F::kIn], o[F::kOut];
+    for (int i = 0; i < F::kIn; ++i)
+        my[64 * i + lane] = v[i];
+    wave_sync();
+    u4 x[F::kIn], o[F::kOut];
 #pragma unroll
-            for (int i = 0; i < F::kIn; ++i)
-                x[i] = my[F::kIn * lane + i];
-            F::apply(x, coef, o);
-            wave_sync();
+    for (int i = 0; i < F::kIn; ++i)
+        x[i] = my[F::kIn * lane + i];
+    F::apply(x, coef, o);
+    wave_sync();
 #pragma unroll
-            for (int i = 0; i < F::kOut; ++i)
-                my[F::kOut * lane + i] = o[i];
-            wave_sync();
-            const int64_t base = t * 64 * F::kOut + lane;
+    for (int i = 0; i < F::kOut; ++i)
+        my[F::kOut * lane + i] = o[i];
+    wave_sync();
+    const int64_t gout = t * 64 * F::kOut + lane;
 #pragma unroll
-            for (int i = 0; i < F::kOut; ++i) {
-                const int64_t g = base + 64 * i;
-                if (whole || g < nout)
-                    st_stream(c + g, my[64 * i + lane]);
-            }
-            wave_sync();
-        }
+    for (int i = 0; i < F::kOut; ++i) {
+        const int64_t g = gout + 64 * i;
+        if (whole || g < nout)
+            st_stream(c + g, my[64 * i + lane]);
     }
 }
 
 // ---------------------------------------------------------------- SoA
-// Thread per (site, link): blockIdx.y is the link j, so b[j] is uniform over
-// the workgroup and lives in scalar registers; each of the 9 plane loads and
-// stores of a wavefront is one contiguous 1 KiB (FP64) or 512 B (FP32) run.
+// Thread per (site, output row): blockIdx.y = 3j + k selects the row, so the
+// link j and the b[j] entries are uniform over the workgroup (scalar
+// registers). A wavefront reads planes (j, k, 0..2) and writes planes
+// (j, k, 0..2), each access one contiguous 1 KiB (FP64) or 512 B (FP32) run.
 template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void fwd_soa(const V *__restrict__ a, const S *__restrict__ b,
                                                   V *__restrict__ c, int64_t n)
 {
-    const int j = blockIdx.y;
+    const int row = blockIdx.y;          // 3j + k
+    const int j = row / 3;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n)
+        return;
     S br[9], bi[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         br[q] = b[2 * (9 * j + q)];
         bi[q] = b[2 * (9 * j + q) + 1];
     }
-    const V *__restrict__ ap = a + (int64_t)(9 * j) * n;
-    V *__restrict__ cp = c + (int64_t)(9 * j) * n;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += step) {
-        V x[9];
+    const V *__restrict__ ap = a + (int64_t)(3 * row) * n + s;
+    V *__restrict__ cp = c + (int64_t)(3 * row) * n + s;
+    V x[3];
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
-            x[q] = ld_stream(ap + q * n + s);
+    for (int m = 0; m < 3; ++m)
+        x[m] = ld_stream(ap + m * n);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) {
+        S re = 0, im = 0;
 #pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                S re = 0, im = 0;
-#pragma unroll
-                for (int m = 0; m < 3; ++m)
-                    cmac(re, im, x[3 * k + m].x, x[3 * k + m].y, br[3 * m + l], bi[3 * m + l]);
-                V o = {re, im};
-                st_stream(cp + (3 * k + l) * n + s, o);
-            }
+        for (int m = 0; m < 3; ++m)
+            cmac(re, im, x[m].x, x[m].y, br[3 * m + l], bi[3 * m + l]);
+        V o = {re, im};
+        st_stream(cp + l * n, o);
     }
 }
 
 // ---------------------------------------------------------------- launchers
-// Workgroups of a forward kernel that fit on one CU at once (registers and
-// LDS permitting), from the runtime's occupancy calculator; cached per device.
-static int occupancy(const void *kernel, std::atomic<int> (&cache)[kMaxDevices])
+// Dynamic LDS to add per workgroup so that at most `waves` wavefronts of
+// `kernel` are resident per CU: the CU's LDS divided by the wanted number of
+// workgroups, minus the kernel's static LDS. Cached per device; 0 when no cap
+// is wanted or a query fails.
+static size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> (&cache)[kMaxDevices])
 {
+    if (waves <= 0)
+        return 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
-        return -1;
-    int n = cache[dev].load(std::memory_order_relaxed);
-    if (n > 0)
-        return n;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kBlock, 0) != hipSuccess || n <= 0)
-        return -1;
-    cache[dev].store(n, std::memory_order_relaxed);
-    return n;
+        return 0;
+    int pad = cache[dev].load(std::memory_order_relaxed);   // pad + 1; 0 = not yet known
+    if (pad > 0)
+        return (size_t)(pad - 1);
+    int lds_cu = 0, lds_block = 0;
+    hipFuncAttributes attr;
+    pad = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        hipFuncGetAttributes(&attr, kernel) == hipSuccess) {
+        // LDS is allocated in granules; round each workgroup's share down to
+        // 1 KiB so that `blocks` of them fit
+        const int blocks = waves * 64 / block > 0 ? waves * 64 / block : 1;
+        const int want = (lds_cu / blocks) / 1024 * 1024 - (int)attr.sharedSizeBytes;
+        const int room = lds_block - (int)attr.sharedSizeBytes;
+        pad = want > 0 ? (want < room ? want : room) : 0;
+    }
+    cache[dev].store(pad + 1, std::memory_order_relaxed);
+    return (size_t)pad;
 }
 
-int fwd_resident_blocks(int precision)
+template <class F>
+static int64_t aos_grid(int64_t sites)
 {
-    static std::atomic<int> c64[kMaxDevices], c32[kMaxDevices], c16[kMaxDevices], c12[kMaxDevices];
+    const int64_t tiles = (sites * F::kUnitsPerSite + 63) / 64;
+    return (tiles + kAosBlock / 64 - 1) / (kAosBlock / 64);
+}
+
+int64_t fwd_aos_grid(int precision, int64_t sites)
+{
     switch (precision) {
-    case 0: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormF64, SU3_UNROLL>), c64);
-    case 1: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormF32, SU3_UNROLL>), c32);
-    case 2: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormBF16, SU3_UNROLL>), c16);
-    default: return occupancy(reinterpret_cast<const void *>(fwd_aos<FormR12, SU3_UNROLL>), c12);
+    case 0: return aos_grid<FormF64>(sites);
+    case 1: return aos_grid<FormF32>(sites);
+    case 2: return aos_grid<FormBF16>(sites);
+    default: return aos_grid<FormR12>(sites);
     }
 }
 
-int soa_resident_blocks(int elem_bytes)
+int64_t fwd_soa_grid(int64_t sites) { return (sites + kBlock - 1) / kBlock; }
+
+template <class F>
+static hipError_t launch_aos(const void *a, const void *b, void *c, int64_t sites, hipStream_t s)
 {
-    static std::atomic<int> c64[kMaxDevices], c32[kMaxDevices];
-    if (elem_bytes == 16)
-        return occupancy(reinterpret_cast<const void *>(fwd_soa<d2, double>), c64);
-    return occupancy(reinterpret_cast<const void *>(fwd_soa<f2, float>), c32);
+    static std::atomic<int> pad_cache[kMaxDevices];
+    const size_t pad = occupancy_pad(reinterpret_cast<const void *>(fwd_aos<F>), F::kWavesPerCU, kAosBlock, pad_cache);
+    return launch_k(fwd_aos<F>, dim3((unsigned)aos_grid<F>(sites)), dim3(kAosBlock), s, pad, (const u4 *)a,
+                    (const typename F::B *)b, (u4 *)c, sites * F::kUnitsPerSite);
 }
 
-hipError_t launch_fwd_aos_f64(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
+hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s)
 {
-    return launch_k(fwd_aos<FormF64, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
-                    (const double *)b, (u4 *)c, sites * FormF64::kUnitsPerSite);
+    switch (precision) {
+    case 0: return launch_aos<FormF64>(a, b, c, sites, s);
+    case 1: return launch_aos<FormF32>(a, b, c, sites, s);
+    case 2: return launch_aos<FormBF16>(a, b, c, sites, s);
+    default: return launch_aos<FormR12>(a, b, c, sites, s);
+    }
 }
 
-hipError_t launch_fwd_aos_f32(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
+hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s)
 {
-    return launch_k(fwd_aos<FormF32, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
-                    (const float *)b, (u4 *)c, sites * FormF32::kUnitsPerSite);
-}
-
-hipError_t launch_fwd_aos_bf16(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
-{
-    return launch_k(fwd_aos<FormBF16, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
-                    (const float *)b, (u4 *)c, sites * FormBF16::kUnitsPerSite);
-}
-
-hipError_t launch_fwd_aos_r12(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s)
-{
-    return launch_k(fwd_aos<FormR12, SU3_UNROLL>, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)a,
-                    (const float *)b, (u4 *)c, sites * FormR12::kUnitsPerSite);
-}
-
-hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, int64_t grid,
-                          hipStream_t s)
-{
-    if (elem_bytes == 16)
-        return launch_k(fwd_soa<d2, double>, dim3((unsigned)grid, 4), dim3(kBlock), s, (const d2 *)a,
-                        (const double *)b, (d2 *)c, sites);
-    return launch_k(fwd_soa<f2, float>, dim3((unsigned)grid, 4), dim3(kBlock), s, (const f2 *)a, (const float *)b,
-                    (f2 *)c, sites);
+    static std::atomic<int> pad64[kMaxDevices], pad32[kMaxDevices];
+    const dim3 grid((unsigned)fwd_soa_grid(sites), 12);
+    if (elem_bytes == 16) {
+        const size_t pad =
+            occupancy_pad(reinterpret_cast<const void *>(fwd_soa<d2, double>), SU3_WAVES_SOA_F64, kBlock, pad64);
+        return launch_k(fwd_soa<d2, double>, grid, dim3(kBlock), s, pad, (const d2 *)a, (const double *)b, (d2 *)c,
+                        sites);
+    }
+    const size_t pad =
+        occupancy_pad(reinterpret_cast<const void *>(fwd_soa<f2, float>), SU3_WAVES_SOA_F32, kBlock, pad32);
+    return launch_k(fwd_soa<f2, float>, grid, dim3(kBlock), s, pad, (const f2 *)a, (const float *)b, (f2 *)c, sites);
 }
 
 } // namespace su3

@@ -60,8 +60,9 @@ constexpr int kMaxDevices = 64;
 
 // Launch a kernel through hipLaunchKernel, which reports a failed launch in
 // its return value; each argument is converted to the kernel's parameter type.
+// dyn_lds is the dynamic LDS size in bytes.
 template <typename... KArgs, typename... Args>
-inline hipError_t launch_k(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args... args)
+inline hipError_t launch_k(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream_t s, size_t dyn_lds, Args... args)
 {
     static_assert(sizeof...(KArgs) == sizeof...(Args), "argument count");
     struct Pack {
@@ -73,29 +74,21 @@ inline hipError_t launch_k(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream
         int i = 0;
         ((argv[i++] = (void *)&e), ...);
     }, p.t);
-    return hipLaunchKernel(reinterpret_cast<const void *>(k), grid, block, argv, 0, s);
+    return hipLaunchKernel(reinterpret_cast<const void *>(k), grid, block, argv, dyn_lds, s);
 }
 
 // ---- launchers (each returns hipSuccess or the launch error) --------------
-// Forward, site-major layout. grid is a multiple of 3 so that the grid-stride
-// step keeps every thread on the same position inside a site.
-hipError_t launch_fwd_aos_f64(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
-hipError_t launch_fwd_aos_f32(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
-hipError_t launch_fwd_aos_bf16(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
-hipError_t launch_fwd_aos_r12(const void *a, const void *b, void *c, int64_t sites, int64_t grid, hipStream_t s);
-// Workgroups of the forward kernel for `precision` (AoS) or of the SoA kernel
-// for `elem_bytes` that can be resident on one CU; <= 0 on a HIP error.
-int fwd_resident_blocks(int precision);
-int soa_resident_blocks(int elem_bytes);
-int copy_resident_blocks();
-// Forward, structure-of-arrays layout.
-hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, int64_t grid,
-                          hipStream_t s);
+// Forward products. The grid covers the lattice once; *_grid report it.
+int64_t fwd_aos_grid(int precision, int64_t sites);
+int64_t fwd_soa_grid(int64_t sites);
+hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s);
+hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s);
+int aos_block_threads();
 // Layout and storage-form conversions.
 hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_bytes, bool to_soa, hipStream_t s);
 hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
-hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, int64_t grid, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
 // Adjoint: stage 1 writes per-workgroup partial sums of db into ws, stage 2
 // reduces them in a fixed order.
 hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,

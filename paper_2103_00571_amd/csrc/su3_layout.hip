@@ -131,23 +131,15 @@ __global__ __launch_bounds__(kBlock) void unpack_r12(const f2 *__restrict__ src,
 }
 
 // ------------------------------------------------------------ stream copy
-// c[i] = a[i] over 16-byte elements: nontemporal 16-byte loads and stores,
-// four elements in flight per thread per iteration.
-__global__ __launch_bounds__(kBlock) void stream_copy(const u4 *__restrict__ src, u4 *__restrict__ dst, int64_t n)
+// dst[i] = src[i] over 16-byte elements, one element per thread, with
+// nontemporal loads and stores; the grid covers the buffer once, so the
+// dispatcher streams it in address order. Workgroups of one wavefront.
+constexpr int kCopyBlock = 64;
+
+__global__ __launch_bounds__(kCopyBlock) void stream_copy(const u4 *__restrict__ src, u4 *__restrict__ dst, int64_t n)
 {
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + 3 * step < n; i += 4 * step) {
-        const u4 v0 = ld_stream(src + i);
-        const u4 v1 = ld_stream(src + i + step);
-        const u4 v2 = ld_stream(src + i + 2 * step);
-        const u4 v3 = ld_stream(src + i + 3 * step);
-        st_stream(dst + i, v0);
-        st_stream(dst + i + step, v1);
-        st_stream(dst + i + 2 * step, v2);
-        st_stream(dst + i + 3 * step, v3);
-    }
-    for (; i < n; i += step)
+    const int64_t i = (int64_t)blockIdx.x * kCopyBlock + threadIdx.x;
+    if (i < n)
         st_stream(dst + i, ld_stream(src + i));
 }
 
@@ -167,34 +159,19 @@ hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_by
     const unsigned g = grid_for(sites, kTileSites);
     if (elem_bytes == 16) {
         if (to_soa)
-            return launch_k(transpose_aos_soa<d2, true>, dim3(g), dim3(kBlock), s, (const d2 *)src, (d2 *)dst, sites);
-        return launch_k(transpose_aos_soa<d2, false>, dim3(g), dim3(kBlock), s, (const d2 *)src, (d2 *)dst, sites);
+            return launch_k(transpose_aos_soa<d2, true>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites);
+        return launch_k(transpose_aos_soa<d2, false>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites);
     }
     if (to_soa)
-        return launch_k(transpose_aos_soa<f2, true>, dim3(g), dim3(kBlock), s, (const f2 *)src, (f2 *)dst, sites);
-    return launch_k(transpose_aos_soa<f2, false>, dim3(g), dim3(kBlock), s, (const f2 *)src, (f2 *)dst, sites);
+        return launch_k(transpose_aos_soa<f2, true>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites);
+    return launch_k(transpose_aos_soa<f2, false>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites);
 }
 
-int copy_resident_blocks()
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
 {
-    static std::atomic<int> cache[kMaxDevices];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
-        return -1;
-    int n = cache[dev].load(std::memory_order_relaxed);
-    if (n > 0)
-        return n;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(stream_copy), kBlock, 0) !=
-            hipSuccess ||
-        n <= 0)
-        return -1;
-    cache[dev].store(n, std::memory_order_relaxed);
-    return n;
-}
-
-hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, int64_t grid, hipStream_t s)
-{
-    return launch_k(stream_copy, dim3((unsigned)grid), dim3(kBlock), s, (const u4 *)src, (u4 *)dst, bytes / 16);
+    const int64_t n = bytes / 16;
+    return launch_k(stream_copy, dim3((unsigned)((n + kCopyBlock - 1) / kCopyBlock)), dim3(kCopyBlock), s, 0,
+                    (const u4 *)src, (u4 *)dst, n);
 }
 
 // precision codes as in su3.h: 0 F64, 1 F32, 2 BF16, 3 R12_F32
@@ -203,15 +180,14 @@ hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision,
     const int64_t elems = sites * 36, links = sites * 4;
     switch (precision) {
     case 1:
-        return launch_k(pack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const d2 *)src, (f2 *)dst, elems);
+        return launch_k(pack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (f2 *)dst, elems);
     case 2:
-        return launch_k(pack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const d2 *)src,
+        return launch_k(pack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const d2 *)src,
                         (uint32_t *)dst, elems);
     case 3:
-        return launch_k(pack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, (const d2 *)src, (f2 *)dst, links);
+        return launch_k(pack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (f2 *)dst, links);
     default:
-        return launch_k(stream_copy, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const u4 *)src, (u4 *)dst,
-                        elems);
+        return launch_stream_copy(src, dst, elems * 16, s);
     }
 }
 
@@ -220,17 +196,16 @@ hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precisio
     const int64_t elems = sites * 36, links = sites * 4;
     switch (precision) {
     case 1:
-        return launch_k(unpack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const f2 *)src, (d2 *)dst,
+        return launch_k(unpack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const f2 *)src, (d2 *)dst,
                         elems);
     case 2:
-        return launch_k(unpack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const uint32_t *)src,
+        return launch_k(unpack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const uint32_t *)src,
                         (d2 *)dst, elems);
     case 3:
-        return launch_k(unpack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, (const f2 *)src, (d2 *)dst,
+        return launch_k(unpack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const f2 *)src, (d2 *)dst,
                         links);
     default:
-        return launch_k(stream_copy, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, (const u4 *)src, (u4 *)dst,
-                        elems);
+        return launch_stream_copy(src, dst, elems * 16, s);
     }
 }
 
