@@ -47,22 +47,6 @@ constexpr int64_t kMaxGridThreads = (int64_t)1 << 32;
 
 bool grid_fits(int64_t blocks, int64_t threads) { return blocks * threads < kMaxGridThreads; }
 
-// Adjoint stage-1 workgroups: a function of the site count only (never of the
-// device), capped, and a multiple of 3.
-// 1023 = 3 x 341 workgroups are resident at once on a 256-CU MI355X (four
-// per CU, bounded by registers and LDS).
-constexpr int64_t kBwdMaxGroups = 1023;
-
-int64_t bwd_groups(int64_t sites)
-{
-    int64_t g = (sites * 12 + kBlock - 1) / kBlock;
-    if (g > kBwdMaxGroups)
-        g = kBwdMaxGroups;
-    if (g < 1)
-        g = 1;
-    return (g + 2) / 3 * 3;
-}
-
 int check_lattice(const void *a, const void *b, const void *c, int64_t sites, int precision, Form &f)
 {
     if (!form_of(precision, f))
@@ -205,7 +189,7 @@ size_t su3_mult_nn_bwd_workspace_bytes(int64_t sites, int precision)
         return 0;
     if (sites <= 0 || sites > kMaxSites)
         return 0;
-    return (size_t)bwd_groups(sites) * 72 * sizeof(double);
+    return (size_t)bwd_groups(sites, precision) * 72 * sizeof(double);
 }
 
 int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, double *db_f64, int64_t sites,
@@ -239,7 +223,7 @@ int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, doub
     hipStream_t s = (hipStream_t)stream;
     if (sites == 0)
         return status_of(launch_bwd_zero(db_f64, s));
-    return status_of(launch_bwd(a, b, dc, da, db_f64, sites, precision, (double *)ws, bwd_groups(sites), s));
+    return status_of(launch_bwd(a, b, dc, da, db_f64, sites, precision, (double *)ws, s));
 }
 
 int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream)

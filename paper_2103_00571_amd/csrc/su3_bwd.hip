@@ -5,104 +5,208 @@
 //   dB[j]    = sum_s A[s][j]^H dC[s][j]     (a sum over every site)
 // The paper has no adjoint; these are the two contractions of its product.
 //
-// Stage 1 (bwd_rows): thread per output row (j, k), the same fixed-position,
-// grid-stride mapping as the forward kernel. Each iteration reads row k of
-// dC[s][j] and of A[s][j], writes row k of dA, and adds
-// conj(A(k, m)) dC(k, l) to nine complex FP64 accumulators (the thread's k
-// and j never change). At the end the workgroup adds its threads' partials in
-// a fixed thread order through LDS and writes one 4x3x3 complex FP64 partial.
-// Stage 2 (bwd_reduce): one workgroup per output component sums the G
-// partials in a fixed strided order and then a fixed binary tree.
-// G depends only on the number of sites, so the rounding sequence, and hence
-// every bit of dB, is the same on every run and every device. No atomics.
+// Stage 1 (bwd_tiles). A thread owns one unit of output rows (FP64: one row,
+// FP32: two rows), as in the forward kernel, and a wavefront streams tiles of
+// 64 units: whole 1 KiB global runs of dC and A, transposed to one unit per
+// lane through LDS. Per row k of link j it writes row k of dA and adds
+// conj(A(k, m)) dC(k, l) (m, l = 0..2) to FP64 accumulators. A wavefront
+// takes kTiles tiles spaced 3 tiles apart, so a lane keeps the same row
+// position (and link) on every tile and its accumulators stay valid; a
+// workgroup of 3 wavefronts covers 3*kTiles consecutive tiles.
+// At the end the lanes' accumulators are summed in a fixed order: per row
+// position within the wavefront (lanes in increasing order), then per link
+// over the workgroup's wavefronts and the link's three rows. Each workgroup
+// writes one 4x3x3 complex FP64 partial, component-major.
+// Stage 2 (bwd_reduce): one workgroup per real component of dB adds the
+// partials in a fixed strided order and a fixed binary tree.
+// The number of workgroups depends only on the number of sites, so the
+// rounding sequence, and every bit of dB, is the same on every run and every
+// device. No atomics.
 #include "su3_internal.hpp"
 
 namespace su3 {
 
-template <typename S>
-struct RowIO;
+constexpr int kBwdWaves = 3;                 // wavefronts per workgroup
+constexpr int kBwdThreads = 64 * kBwdWaves;
+#ifndef SU3_BWD_TILES
+#define SU3_BWD_TILES 8
+#endif
+constexpr int kTiles = SU3_BWD_TILES;        // tiles per wavefront
 
-template <>
-struct RowIO<double> {
-    typedef d2 V;
+// FP64: unit = one row (3 complex, 48 B); 12 units per site.
+struct BwdF64 {
+    typedef double S;
+    static constexpr int kRows = 1, kUnitsPerSite = 12;
 };
-template <>
-struct RowIO<float> {
-    typedef f2 V;
+// FP32: unit = two rows (6 complex float, 48 B); 6 units per site.
+struct BwdF32 {
+    typedef float S;
+    static constexpr int kRows = 2, kUnitsPerSite = 6;
 };
 
-template <typename S>
-__global__ __launch_bounds__(kBlock) void bwd_rows(const typename RowIO<S>::V *__restrict__ a,
-                                                   const S *__restrict__ b,
-                                                   const typename RowIO<S>::V *__restrict__ dc,
-                                                   typename RowIO<S>::V *__restrict__ da, double *__restrict__ ws,
-                                                   int64_t rows)
+// Order LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync_bwd()
 {
-    typedef typename RowIO<S>::V V;
-    __shared__ double part[kBlock][19]; // 18 used; odd stride spreads banks
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    const int j = (int)((first % 12) / 3);
-    S br[9], bi[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        br[q] = b[2 * (9 * j + q)];
-        bi[q] = b[2 * (9 * j + q) + 1];
-    }
-    double accr[9], acci[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        accr[q] = 0.0;
-        acci[q] = 0.0;
-    }
+template <class F>
+__global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ a, const typename F::S *__restrict__ b,
+                                                         const u4 *__restrict__ dc, u4 *__restrict__ da,
+                                                         double *__restrict__ ws, int64_t units, int64_t groups)
+{
+    typedef typename F::S S;
+    typedef S SV __attribute__((ext_vector_type(16 / sizeof(S))));
+    constexpr int PV = 16 / sizeof(S);        // scalars per 16-byte chunk
+    constexpr int R = F::kRows;
+    constexpr int NV = 18 * R;                // accumulator doubles per lane
+    constexpr int P = F::kUnitsPerSite;
+    constexpr int kStageBytes = 2 * 3 * 64 * 16;     // a and dC tiles
+    constexpr int kRedBytes = 64 * (NV + 1) * 8;     // lane vectors, padded rows
+    constexpr int kBytes = kStageBytes > kRedBytes ? kStageBytes : kRedBytes;
+    // per-wavefront scratch: tile staging in the loop, reduction after it
+    __shared__ __attribute__((aligned(16))) char scratch[kBwdWaves][kBytes];
+    __shared__ double rowsum[kBwdWaves][12 * 18];
+    __shared__ S bsh[72];
 
-    for (int64_t r = first; r < rows; r += step) {
-        V g[3], x[3];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    u4 *stage = reinterpret_cast<u4 *>(scratch[wv]);
+    double *red = reinterpret_cast<double *>(scratch[wv]);
+    const int64_t t0 = (int64_t)blockIdx.x * kBwdWaves * kTiles + wv;
+    const int64_t nchunks = units * 3;
+
+    if (threadIdx.x < 72)
+        bsh[threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
+
+    const int pos = (int)((t0 * 64 + lane) % P);   // unit position in the site
+    // row h of the unit is site row R*pos + h, which belongs to link (R*pos+h)/3
+    S br[R][9], bi[R][9];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            g[l] = ld_stream(dc + 3 * r + l);
-            x[l] = ld_stream(a + 3 * r + l);
+    for (int h = 0; h < R; ++h) {
+        const int j = (R * pos + h) / 3;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            br[h][q] = bsh[2 * (9 * j + q)];
+            bi[h][q] = bsh[2 * (9 * j + q) + 1];
         }
-        // dA(k, m) = sum_l dC(k, l) conj(B(m, l))
+    }
+    double acc[NV];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            S re = 0, im = 0;
+    for (int v = 0; v < NV; ++v)
+        acc[v] = 0.0;
+
+    for (int k = 0; k < kTiles; ++k) {
+        const int64_t t = t0 + (int64_t)kBwdWaves * k;
+        if (t * 64 >= units)
+            break;                                   // wave-uniform
+        const bool whole = (t + 1) * 64 <= units;
+        const int64_t g0 = t * 64 * 3 + lane;
+        u4 va[3], vg[3];
 #pragma unroll
-            for (int l = 0; l < 3; ++l)
-                cmac(re, im, g[l].x, g[l].y, br[3 * m + l], -bi[3 * m + l]);
-            V o = {re, im};
-            st_stream(da + 3 * r + m, o);
+        for (int i = 0; i < 3; ++i) {
+            const int64_t g = g0 + 64 * i;
+            const int64_t gc = g < nchunks ? g : nchunks - 1;   // in bounds; unused past the end
+            vg[i] = ld_stream(dc + gc);
+            va[i] = ld_stream(a + gc);
         }
-        // dB(m, l) += conj(A(k, m)) dC(k, l), in FP64
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < 3; ++i) {
+            stage[64 * i + lane] = vg[i];
+            stage[192 + 64 * i + lane] = va[i];
+        }
+        wave_sync_bwd();
+        S g[6 * R], x[6 * R];   // interleaved re/im of the unit's R rows
 #pragma unroll
-            for (int l = 0; l < 3; ++l)
-                cmac(accr[3 * m + l], acci[3 * m + l], (double)x[m].x, -(double)x[m].y, (double)g[l].x,
-                     (double)g[l].y);
+        for (int i = 0; i < 3; ++i) {
+            const SV wg = __builtin_bit_cast(SV, stage[3 * lane + i]);
+            const SV wa = __builtin_bit_cast(SV, stage[192 + 3 * lane + i]);
+#pragma unroll
+            for (int e = 0; e < PV; ++e) {
+                g[PV * i + e] = wg[e];
+                x[PV * i + e] = wa[e];
+            }
+        }
+        // dA(k, m) = sum_l dC(k, l) conj(B(m, l)), per row h of the unit
+        S o[6 * R];
+#pragma unroll
+        for (int h = 0; h < R; ++h)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                S re = 0, im = 0;
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    cmac(re, im, g[6 * h + 2 * l], g[6 * h + 2 * l + 1], br[h][3 * m + l], -bi[h][3 * m + l]);
+                o[6 * h + 2 * m] = re;
+                o[6 * h + 2 * m + 1] = im;
+            }
+        // dB(m, l) += conj(A(k, m)) dC(k, l), in FP64; lanes past the end of a
+        // ragged last tile hold re-read data and add nothing
+        const bool live = whole || t * 64 + lane < units;
+#pragma unroll
+        for (int h = 0; h < 6 * R; ++h)
+            x[h] = live ? x[h] : S(0);
+#pragma unroll
+        for (int h = 0; h < R; ++h)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    cmac(acc[18 * h + 6 * m + 2 * l], acc[18 * h + 6 * m + 2 * l + 1], (double)x[6 * h + 2 * m],
+                         -(double)x[6 * h + 2 * m + 1], (double)g[6 * h + 2 * l], (double)g[6 * h + 2 * l + 1]);
+        wave_sync_bwd();
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            SV w;
+#pragma unroll
+            for (int e = 0; e < PV; ++e)
+                w[e] = o[PV * i + e];
+            stage[3 * lane + i] = __builtin_bit_cast(u4, w);
+        }
+        wave_sync_bwd();
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int64_t gi = g0 + 64 * i;
+            if (whole || gi < nchunks)
+                st_stream(da + gi, stage[64 * i + lane]);
+        }
+        wave_sync_bwd();
     }
 
+    // ---- fixed-order reduction --------------------------------------------
+    // lane vectors -> LDS (row stride NV + 1 doubles)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        part[threadIdx.x][2 * q] = accr[q];
-        part[threadIdx.x][2 * q + 1] = acci[q];
+    for (int v = 0; v < NV; ++v)
+        red[lane * (NV + 1) + v] = acc[v];
+    wave_sync_bwd();
+    // row sums: output o = 18*r + e for site row r = 0..11. The lane at unit
+    // position w holds rows R*w .. R*w+R-1; the lanes at position w are
+    // (w - base) mod P and every P-th lane after it, added in increasing order.
+    const int base = (int)((t0 * 64) % P);
+    for (int o2 = lane; o2 < 12 * 18; o2 += 64) {
+        const int r = o2 / 18, e = o2 % 18;
+        const int w = r / R, v = 18 * (r % R) + e;
+        double sum = 0.0;
+        for (int l = ((w - base) % P + P) % P; l < 64; l += P)
+            sum += red[l * (NV + 1) + v];
+        rowsum[wv][o2] = sum;
     }
     __syncthreads();
+    // workgroup partial of component q = 18*j + e: wavefronts in order, then
+    // the link's three rows in order
     if (threadIdx.x < 72) {
-        // component q = jj*18 + e of this workgroup's partial: the threads
-        // whose link is jj, added in increasing thread order
-        const int jj = threadIdx.x / 18, e = threadIdx.x % 18;
-        const int64_t base = (int64_t)blockIdx.x * kBlock;
+        const int j = threadIdx.x / 18, e = threadIdx.x % 18;
         double sum = 0.0;
-        for (int t = 0; t < kBlock; ++t)
-            if ((int)(((base + t) % 12) / 3) == jj)
-                sum += part[t][e];
-        ws[(int64_t)blockIdx.x * 72 + threadIdx.x] = sum;
+        for (int w2 = 0; w2 < kBwdWaves; ++w2)
+            for (int r = 3 * j; r < 3 * j + 3; ++r)
+                sum += rowsum[w2][18 * r + e];
+        ws[(int64_t)threadIdx.x * groups + blockIdx.x] = sum;
     }
 }
 
-// grid = 72 workgroups, one per real component of dB
+// grid = 72 workgroups, one per real component of dB; ws is component-major
 __global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ ws, double *__restrict__ db,
                                                      int64_t groups)
 {
@@ -110,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ 
     const int q = blockIdx.x;
     double sum = 0.0;
     for (int64_t g = threadIdx.x; g < groups; g += kBlock)
-        sum += ws[g * 72 + q];
+        sum += ws[(int64_t)q * groups + g];
     red[threadIdx.x] = sum;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -122,16 +226,26 @@ __global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ 
         db[q] = red[0];
 }
 
-hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
-                      int precision, double *ws, int64_t groups, hipStream_t s)
+// Workgroups of stage 1 for `sites` (a function of the size only).
+int64_t bwd_groups(int64_t sites, int precision)
 {
+    const int64_t units = sites * (precision == 0 ? BwdF64::kUnitsPerSite : BwdF32::kUnitsPerSite);
+    const int64_t tiles = (units + 63) / 64;
+    const int64_t per = (int64_t)kBwdWaves * kTiles;
+    return (tiles + per - 1) / per;
+}
+
+hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
+                      int precision, double *ws, hipStream_t s)
+{
+    const int64_t groups = bwd_groups(sites, precision);
     hipError_t e;
     if (precision == 0)
-        e = launch_k(bwd_rows<double>, dim3((unsigned)groups), dim3(kBlock), s, 0, (const d2 *)a, (const double *)b,
-                     (const d2 *)dc, (d2 *)da, ws, sites * 12);
+        e = launch_k(bwd_tiles<BwdF64>, dim3((unsigned)groups), dim3(kBwdThreads), s, 0, (const u4 *)a,
+                     (const double *)b, (const u4 *)dc, (u4 *)da, ws, sites * BwdF64::kUnitsPerSite, groups);
     else
-        e = launch_k(bwd_rows<float>, dim3((unsigned)groups), dim3(kBlock), s, 0, (const f2 *)a, (const float *)b,
-                     (const f2 *)dc, (f2 *)da, ws, sites * 12);
+        e = launch_k(bwd_tiles<BwdF32>, dim3((unsigned)groups), dim3(kBwdThreads), s, 0, (const u4 *)a,
+                     (const float *)b, (const u4 *)dc, (u4 *)da, ws, sites * BwdF32::kUnitsPerSite, groups);
     if (e != hipSuccess)
         return e;
     return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)ws, db, groups);

@@ -94,8 +94,13 @@ def test_bwd_validation(abi):
     assert ws_need > 0 and ws_need % 16 == 0
     assert abi.su3_mult_nn_bwd_workspace_bytes(1000, 2) == 0
     assert abi.su3_mult_nn_bwd_workspace_bytes(0, 0) == 0
-    # group count depends only on the site count, never on the device
-    assert abi.su3_mult_nn_bwd_workspace_bytes(10 ** 7, 0) == abi.su3_mult_nn_bwd_workspace_bytes(10 ** 7, 1)
+    # the workspace (72 FP64 partials per stage-1 workgroup) is a function of
+    # the size and form only -- queried here with no GPU present -- and grows
+    # with the lattice
+    for form in (0, 1):
+        w = [abi.su3_mult_nn_bwd_workspace_bytes(n, form) for n in (1, 10 ** 4, 10 ** 7)]
+        assert all(x % (72 * 8) == 0 for x in w) and w[0] <= w[1] <= w[2]
+        assert w == [abi.su3_mult_nn_bwd_workspace_bytes(n, form) for n in (1, 10 ** 4, 10 ** 7)]
     D, DA, DB, WS = 1 << 41, 1 << 42, 1 << 43, 1 << 44
     f = abi.su3_mult_nn_bwd
     assert f(A, B, D, DA, DB, 1000, 2, WS, ws_need, None) == abi.SU3_ERR_PRECISION
