@@ -65,9 +65,11 @@ def time_launches(fn, steps: int, warmup: int, torch) -> float:
     return start.elapsed_time(stop) / steps
 
 
-def traffic_record(bytes_alg: float):
-    """HBM traffic per launch of the FP64 AoS kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+def traffic_record():
+    """HBM bytes per launch of the FP64 AoS kernel at L=48 from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by what
+    it reads for the streaming copy of known size), or None if the summary is
+    missing or was taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -230,12 +232,15 @@ def main() -> int:
             results[name]["err_sample_sites"] = int(idx.size)
 
     # ---- roofline of the dominant kernel ---------------------------------------
-    achieved = BYTES_PER_SITE["f64"] * sites / (ms64 * 1e-3) / 1e9
-    traffic = traffic_record(BYTES_PER_SITE["f64"] * sites)
+    alg_bytes = BYTES_PER_SITE["f64"] * sites
+    achieved = alg_bytes / (ms64 * 1e-3) / 1e9
+    traffic = traffic_record() if L == 48 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "fwd_aos_f64", "bytes_per_launch": BYTES_PER_SITE["f64"] * sites,
-                "grid": grid, "block": block}
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes,
+                "kernel": "su3::fwd_aos<FormF64>", "algorithmic_bytes_per_launch": alg_bytes,
+                "bytes_per_site": BYTES_PER_SITE["f64"], "grid": grid, "block": block}
     if "copy" in results:
         roofline["frac_of_measured_copy"] = achieved / results["copy"]["gb_s"]
 
