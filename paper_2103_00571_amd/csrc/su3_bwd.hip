@@ -32,6 +32,14 @@ constexpr int kBwdThreads = 64 * kBwdWaves;
 #define SU3_BWD_TILES 8
 #endif
 constexpr int kTiles = SU3_BWD_TILES;        // tiles per wavefront
+// Resident wavefronts per CU for stage 1 (0: as many as fit). 9 wavefronts
+// (54 KiB of tile loads in flight per CU) measured best at L=32.
+#ifndef SU3_BWD_WAVES_F64
+#define SU3_BWD_WAVES_F64 9
+#endif
+#ifndef SU3_BWD_WAVES_F32
+#define SU3_BWD_WAVES_F32 9
+#endif
 
 // FP64: unit = one row (3 complex, 48 B); 12 units per site.
 struct BwdF64 {
@@ -238,14 +246,20 @@ int64_t bwd_groups(int64_t sites, int precision)
 hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
                       int precision, double *ws, hipStream_t s)
 {
+    static std::atomic<int> pad64[kMaxDevices], pad32[kMaxDevices];
     const int64_t groups = bwd_groups(sites, precision);
     hipError_t e;
-    if (precision == 0)
-        e = launch_k(bwd_tiles<BwdF64>, dim3((unsigned)groups), dim3(kBwdThreads), s, 0, (const u4 *)a,
+    if (precision == 0) {
+        const size_t pad =
+            occupancy_pad(reinterpret_cast<const void *>(bwd_tiles<BwdF64>), SU3_BWD_WAVES_F64, kBwdThreads, pad64);
+        e = launch_k(bwd_tiles<BwdF64>, dim3((unsigned)groups), dim3(kBwdThreads), s, pad, (const u4 *)a,
                      (const double *)b, (const u4 *)dc, (u4 *)da, ws, sites * BwdF64::kUnitsPerSite, groups);
-    else
-        e = launch_k(bwd_tiles<BwdF32>, dim3((unsigned)groups), dim3(kBwdThreads), s, 0, (const u4 *)a,
+    } else {
+        const size_t pad =
+            occupancy_pad(reinterpret_cast<const void *>(bwd_tiles<BwdF32>), SU3_BWD_WAVES_F32, kBwdThreads, pad32);
+        e = launch_k(bwd_tiles<BwdF32>, dim3((unsigned)groups), dim3(kBwdThreads), s, pad, (const u4 *)a,
                      (const float *)b, (const u4 *)dc, (u4 *)da, ws, sites * BwdF32::kUnitsPerSite, groups);
+    }
     if (e != hipSuccess)
         return e;
     return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)ws, db, groups);

@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void fwd_soa(const V *__restrict__ a, const
 // `kernel` are resident per CU: the CU's LDS divided by the wanted number of
 // workgroups, minus the kernel's static LDS. Cached per device; 0 when no cap
 // is wanted or a query fails.
-static size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> (&cache)[kMaxDevices])
+size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> (&cache)[kMaxDevices])
 {
     if (waves <= 0)
         return 0;

@@ -77,6 +77,11 @@ inline hipError_t launch_k(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream
     return hipLaunchKernel(reinterpret_cast<const void *>(k), grid, block, argv, dyn_lds, s);
 }
 
+// Dynamic LDS to add to each workgroup of `kernel` (block threads each) so
+// that at most `waves` wavefronts are resident per CU; 0 for no cap. Cached
+// per device in `cache` (entries start at 0).
+size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> (&cache)[kMaxDevices]);
+
 // ---- launchers (each returns hipSuccess or the launch error) --------------
 // Forward products. The grid covers the lattice once; *_grid report it.
 int64_t fwd_aos_grid(int precision, int64_t sites);
