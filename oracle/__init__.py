@@ -61,6 +61,10 @@ def _bind(path: str) -> ctypes.CDLL:
         "su3o_mult_nn_bf16": ([P, P, P, I64], None),
         "su3o_mult_nn_r12": ([P, P, P, I64], None),
         "su3o_aos_to_soa": ([P, P, I64, I32], None),
+        "su3o_mult_na": ([P, P, P, I64], None),
+        "su3o_mult_an": ([P, P, P, I64], None),
+        "su3o_mult_nn_r12_f64": ([P, P, P, I64], None),
+        "su3o_mat_vec": ([P, P, P, I64], None),
         "su3o_soa_to_aos": ([P, P, I64, I32], None),
     }
     for name, (args, res) in sig.items():
@@ -237,8 +241,44 @@ class Oracle:
         self.lib.su3o_soa_to_aos(_p(x), _p(out), sites, x.dtype.itemsize)
         return out
 
+    # O7-O9 ----------------------------------------------------------------
+    def mult_na(self, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+        """c = a b^H per site and link."""
+        a = _c128(a, (4, 3, 3))
+        b = _c128(b, (4, 3, 3))
+        c = np.empty_like(a)
+        self.lib.su3o_mult_na(_p(a), _p(b), _p(c), a.shape[0])
+        return c
+
+    def mult_an(self, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+        """c = a^H b per site and link."""
+        a = _c128(a, (4, 3, 3))
+        b = _c128(b, (4, 3, 3))
+        c = np.empty_like(a)
+        self.lib.su3o_mult_an(_p(a), _p(b), _p(c), a.shape[0])
+        return c
+
+    def mult_nn_r12_f64(self, a12: np.ndarray, b: np.ndarray) -> np.ndarray:
+        """Reconstruct-12 product in FP64: a12 is (sites, 4, 2, 3)."""
+        a12 = _c128(a12, (4, 2, 3))
+        b = _c128(b, (4, 3, 3))
+        c = np.empty((a12.shape[0], 4, 3, 3), dtype=np.complex128)
+        self.lib.su3o_mult_nn_r12_f64(_p(a12), _p(b), _p(c), a12.shape[0])
+        return c
+
+    def mat_vec(self, a: np.ndarray, v: np.ndarray) -> np.ndarray:
+        """w[s][j] = a[s][j] v[s]; v is (sites, 3), w is (sites, 4, 3)."""
+        a = _c128(a, (4, 3, 3))
+        v = np.ascontiguousarray(v, dtype=np.complex128)
+        if v.shape != (a.shape[0], 3):
+            raise ValueError("v must be (sites, 3)")
+        w = np.empty((a.shape[0], 4, 3), dtype=np.complex128)
+        self.lib.su3o_mat_vec(_p(a), _p(v), _p(w), a.shape[0])
+        return w
+
 
 _default: Oracle | None = None
+
 
 
 def default() -> Oracle:

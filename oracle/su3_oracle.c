@@ -20,6 +20,12 @@
  *     (s*4 + j)*9, i.e. shape (sites, 4, 3, 3);
  *   - b is (4, 3, 3): b[j] multiplies link j of every site.
  *
+ * Beyond the paper's product the oracle also defines the two other products
+ * of the MILC family the benchmark is drawn from (a b^H and a^H b, the
+ * adjoint's contractions), the reconstruct-12 product in FP64, and the SU(3)
+ * matrix times colour-vector product the paper names as the other building
+ * block (section Introduction).
+ *
  * Parity status: every function here is pinned by a CPU test against facts
  * fixed by the paper or by the mathematics (identity and signed-permutation
  * products, the paper's constant initialisation, exact rational arithmetic,
@@ -393,4 +399,93 @@ void su3o_soa_to_aos(const void *src, void *dst, int64_t sites, int elem_bytes)
         for (int p = 0; p < SITE_C; ++p)
             memcpy(D + (s * SITE_C + p) * elem_bytes,
                    S + ((int64_t)p * sites + s) * elem_bytes, (size_t)elem_bytes);
+}
+
+/* ------------------------------------------------------------------ O7 --
+ * The other two link products. na: c[s][j] = a[s][j] * b[j]^H, i.e.
+ * c(k, l) = sum_m a(k, m) conj(b(l, m)). an: c[s][j] = a[s][j]^H * b[j], i.e.
+ * c(k, l) = sum_m conj(a(m, k)) b(m, l). Same loop order as O1.
+ */
+void su3o_mult_na(const double *a, const double *b, double *c, int64_t sites)
+{
+    for (int64_t i = 0; i < sites; ++i)
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) {
+                    double re = 0.0, im = 0.0;
+                    for (int m = 0; m < 3; ++m) {
+                        const double ar = a[ix(i, j, k, m)];
+                        const double ai = a[ix(i, j, k, m) + 1];
+                        const double br = b[bx(j, l, m)];
+                        const double bi = -b[bx(j, l, m) + 1];
+                        re += ar * br - ai * bi;
+                        im += ar * bi + ai * br;
+                    }
+                    c[ix(i, j, k, l)] = re;
+                    c[ix(i, j, k, l) + 1] = im;
+                }
+}
+
+void su3o_mult_an(const double *a, const double *b, double *c, int64_t sites)
+{
+    for (int64_t i = 0; i < sites; ++i)
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) {
+                    double re = 0.0, im = 0.0;
+                    for (int m = 0; m < 3; ++m) {
+                        const double ar = a[ix(i, j, m, k)];
+                        const double ai = -a[ix(i, j, m, k) + 1];
+                        const double br = b[bx(j, m, l)];
+                        const double bi = b[bx(j, m, l) + 1];
+                        re += ar * br - ai * bi;
+                        im += ar * bi + ai * br;
+                    }
+                    c[ix(i, j, k, l)] = re;
+                    c[ix(i, j, k, l) + 1] = im;
+                }
+}
+
+/* ------------------------------------------------------------------ O8 --
+ * Reconstruct-12 in FP64: a holds rows 0-1 of every link in FP64, shape
+ * (sites, 4, 2, 3) complex; row 2 is rebuilt by O3, then the O1 product.
+ */
+void su3o_mult_nn_r12_f64(const double *a12, const double *b, double *c, int64_t sites)
+{
+    double aw[72];
+    for (int64_t s = 0; s < sites; ++s) {
+        for (int j = 0; j < 4; ++j) {
+            const double *R = a12 + 12 * (s * 4 + j);   /* rows 0-1: 6 complex */
+            double *L = aw + 18 * j;                     /* full link: 9 complex */
+            for (int q = 0; q < 12; ++q)
+                L[q] = R[q];
+            su3o_recon_row2(L, L + 6, L + 12);
+        }
+        su3o_mult_nn(aw, b, c + 72 * s, 1);
+    }
+}
+
+/* ------------------------------------------------------------------ O9 --
+ * SU(3) matrix times colour vector over the lattice (the matrix-vector
+ * building block; section Introduction): every link of a site applied to the
+ * site's own colour vector, w[s][j](k) = sum_m a[s][j](k, m) v[s](m).
+ * v is (sites, 3) complex, w is (sites, 4, 3) complex.
+ */
+void su3o_mat_vec(const double *a, const double *v, double *w, int64_t sites)
+{
+    for (int64_t i = 0; i < sites; ++i)
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 3; ++k) {
+                double re = 0.0, im = 0.0;
+                for (int m = 0; m < 3; ++m) {
+                    const double ar = a[ix(i, j, k, m)];
+                    const double ai = a[ix(i, j, k, m) + 1];
+                    const double vr = v[2 * (3 * i + m)];
+                    const double vi = v[2 * (3 * i + m) + 1];
+                    re += ar * vr - ai * vi;
+                    im += ar * vi + ai * vr;
+                }
+                w[2 * ((i * 4 + j) * 3 + k)] = re;
+                w[2 * ((i * 4 + j) * 3 + k) + 1] = im;
+            }
 }

@@ -51,6 +51,16 @@ MUTANTS = [
      "memcpy(D + (s * SITE_C + p) * elem_bytes,"),
     ("pack_r12_wrong_row", "su3o_pack_r12(", "dst[o] = (float)src[ix(s, j, k, l)];",
      "dst[o] = (float)src[ix(s, j, k + 1, l)];"),
+    ("na_no_conj", "su3o_mult_na(", "const double bi = -b[bx(j, l, m) + 1];",
+     "const double bi = b[bx(j, l, m) + 1];"),
+    ("na_not_transposed", "su3o_mult_na(", "b[bx(j, l, m)]", "b[bx(j, m, l)]"),
+    ("an_no_conj", "su3o_mult_an(", "const double ai = -a[ix(i, j, m, k) + 1];",
+     "const double ai = a[ix(i, j, m, k) + 1];"),
+    ("an_not_transposed", "su3o_mult_an(", "a[ix(i, j, m, k)]", "a[ix(i, j, k, m)]"),
+    ("r12f64_rows_swapped", "su3o_mult_nn_r12_f64(", "su3o_recon_row2(L, L + 6, L + 12);",
+     "su3o_recon_row2(L + 6, L, L + 12);"),
+    ("matvec_sign", "su3o_mat_vec(", "re += ar * vr - ai * vi;", "re += ar * vr + ai * vi;"),
+    ("matvec_wrong_site", "su3o_mat_vec(", "v[2 * (3 * i + m)]", "v[2 * (3 * ((i + 1) % sites) + m)]"),
 ]
 
 
@@ -63,12 +73,18 @@ def _mutate(src: str, func: str, old: str, new: str) -> str:
     return src[:start] + body.replace(old, new) + src[end:]
 
 
+PIN_MODULES = ("test_oracle_pins.py", "test_oracle_next.py")
+
+
 def _pins():
-    spec = importlib.util.spec_from_file_location("oracle_pins", os.path.join(HERE, "test_oracle_pins.py"))
-    mod = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mod)
-    return [f for name, f in sorted(vars(mod).items())
-            if name.startswith("test_") and "O" in inspect.signature(f).parameters]
+    pins = []
+    for fname in PIN_MODULES:
+        spec = importlib.util.spec_from_file_location(fname[:-3], os.path.join(HERE, fname))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        pins += [f for name, f in sorted(vars(mod).items())
+                 if name.startswith("test_") and "O" in inspect.signature(f).parameters]
+    return pins
 
 
 @pytest.mark.parametrize("name,func,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
