@@ -31,7 +31,8 @@ METRIC = "SU(3) link-mult sites/s & % HBM peak, L=48 FP64 vs FP32/recon-12"
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 FLOP_PER_SITE = 864            # paper's count: 4 x 27 x (4 mul + 4 add)
 # algorithmic bytes per site: a read once + c written once (b ignored)
-BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "f32": 576, "bf16": 288, "r12": 480}
+BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "f32": 576, "bf16": 288, "r12": 480,
+                  "r12c": 384, "r12f64": 960, "na": 1152, "an": 1152, "matvec": 816}
 BWD_BYTES_PER_SITE = {"f64": 3 * 576, "f32": 3 * 288}   # a, dC read; dA written
 KERNEL_SOURCES = ["paper_2103_00571_amd/csrc/su3_fwd.hip", "paper_2103_00571_amd/csrc/su3_internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_aos_f64_L48.json")
@@ -112,7 +113,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
-    ap.add_argument("--forms", default="f64,soa,f32,bf16,r12,copy,bwd")
+    ap.add_argument("--forms", default="f64,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -195,7 +196,36 @@ def main() -> int:
         record(name, ms, BYTES_PER_SITE[name], sites)
         outputs[name] = y
         del x
-    for name in ("f32", "bf16", "r12", "soa"):
+    # ---- compressed-output and FP64 reconstruct-12 -------------------------
+    if "r12c" in forms:
+        x = ops.pack(ta, ops.SU3_R12C_F32)
+        y = ops.mult_nn(x, tb32, form=ops.SU3_R12C_F32)
+        ms = time_launches(lambda: ops.mult_nn(x, tb32, out=y, form=ops.SU3_R12C_F32), args.steps, args.warmup,
+                           torch)
+        record("r12c", ms, BYTES_PER_SITE["r12c"], sites)
+        outputs["r12c"] = ops.unpack(y, ops.SU3_R12C_F32)   # product with row 2 rebuilt, for the error report
+        del x, y
+    if "r12f64" in forms:
+        x = ops.pack(ta, ops.SU3_R12_F64)
+        y = ops.mult_nn(x, tb64)
+        ms = time_launches(lambda: ops.mult_nn(x, tb64, out=y), args.steps, args.warmup, torch)
+        record("r12f64", ms, BYTES_PER_SITE["r12f64"], sites)
+        outputs["r12f64"] = y
+        del x
+    # ---- the other products (FP64): a b^H, a^H b, matrix x colour vector -------
+    for name, fn in (("na", ops.mult_na), ("an", ops.mult_an)):
+        if name in forms:
+            y = torch.empty_like(ta)
+            ms = time_launches(lambda: fn(ta, tb64, out=y), args.steps, args.warmup, torch)
+            record(name, ms, BYTES_PER_SITE[name], sites)
+            del y
+    if "matvec" in forms:
+        tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=4)[:, 0, 0, :].copy()).to(dev)
+        w = ops.mat_vec(ta, tv)
+        ms = time_launches(lambda: ops.mat_vec(ta, tv, out=w), args.steps, args.warmup, torch)
+        record("matvec", ms, BYTES_PER_SITE["matvec"], sites)
+        del tv, w
+    for name in ("f32", "bf16", "r12", "r12c", "r12f64", "soa"):
         if name in results:
             results[name]["speedup_vs_f64"] = ms64 / results[name]["ms"]
 

@@ -43,10 +43,17 @@
  *  SU3_R12_F32  rows 0-1 only: 4x2x3 cfloat, 4x3x3 cfloat      288 B, full FP32
  *               192 B; row 2 is rebuilt as
  *               conj(row0 x row1)
- * FP32, BF16 and R12 compute in FP32; FP64 computes in FP64. BF16 results are
- * rounded to nearest, ties to even. The reconstruct-12 form is valid for
- * links in SU(3), for which the third row equals the conjugate cross product
- * of the first two.
+ *  SU3_R12C_F32 rows 0-1 only, as above  4x3x3 cfloat      rows 0-1 only: 4x2x3
+ *               (192 B)                                     cfloat, 192 B
+ *  SU3_R12_F64  rows 0-1 only: 4x2x3     4x3x3 cdouble     576 B, full FP64
+ *               complex double, 384 B
+ * FP32, BF16, R12_F32 and R12C_F32 compute in FP32; FP64 and R12_F64 compute
+ * in FP64. BF16 results are rounded to nearest, ties to even. The
+ * reconstruct-12 forms are valid for links in SU(3), for which the third row
+ * equals the conjugate cross product of the first two. R12C_F32 keeps the
+ * product compressed too: rows 0-1 of a*b are rows 0-1 of a times b, and the
+ * product of SU(3) matrices is in SU(3), so its third row can be rebuilt the
+ * same way (su3_unpack).
  */
 #ifndef SU3_H
 #define SU3_H
@@ -58,14 +65,16 @@
 extern "C" {
 #endif
 
-#define SU3_ABI_VERSION 1
+#define SU3_ABI_VERSION 2
 
 /* storage form codes */
 enum su3_precision {
     SU3_F64 = 0,
     SU3_F32 = 1,
     SU3_BF16 = 2,
-    SU3_R12_F32 = 3
+    SU3_R12_F32 = 3,
+    SU3_R12C_F32 = 4,
+    SU3_R12_F64 = 5
 };
 
 /* status codes */
@@ -101,6 +110,35 @@ int su3_mult_nn(const void *a, const void *b, void *c, int64_t sites,
                 int precision, void *stream);
 
 /*
+ * The two other link products of the MILC family the benchmark is drawn
+ * from (they are also the two contractions of the adjoint):
+ *   su3_mult_na: c[s][j] = a[s][j] * b[j]^H,  c(k, l) = sum_m a(k, m) conj(b(l, m))
+ *   su3_mult_an: c[s][j] = a[s][j]^H * b[j],  c(k, l) = sum_m conj(a(m, k)) b(m, l)
+ * Site-major layout, SU3_F64 and SU3_F32 only (other forms return
+ * SU3_ERR_PRECISION); arguments, alignment, overlap and errors as
+ * su3_mult_nn.
+ */
+int su3_mult_na(const void *a, const void *b, void *c, int64_t sites,
+                int precision, void *stream);
+int su3_mult_an(const void *a, const void *b, void *c, int64_t sites,
+                int precision, void *stream);
+
+/*
+ * SU(3) matrix times colour vector, the matrix-vector building block named
+ * beside the matrix-matrix product (arXiv 2103.00571, section Introduction):
+ * every link of a site applied to the site's own colour vector,
+ *   w[s][j](k) = sum_m a[s][j](k, m) v[s](m),   j = 0..3.
+ * a: site-major links, (sites, 4, 3, 3) complex, 16-byte aligned.
+ * v: one colour vector per site, (sites, 3) complex, 8-byte aligned.
+ * w: (sites, 4, 3) complex, 16-byte aligned, overlapping neither input.
+ * SU3_F64 (complex double) and SU3_F32 (complex float) only.
+ * Errors: SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION,
+ * SU3_ERR_OVERLAP, SU3_ERR_HIP.
+ */
+int su3_mat_vec(const void *a, const void *v, void *w, int64_t sites,
+                int precision, void *stream);
+
+/*
  * The same product on the SoA layout: a and c are 36 planes of `sites`
  * complex elements. Supports SU3_F64 and SU3_F32 (other forms return
  * SU3_ERR_PRECISION). Same alignment, overlap and error rules as
@@ -123,12 +161,15 @@ int su3_soa_to_aos(const void *src, void *dst, int64_t sites, int precision,
  * Conversion from FP64 AoS links to a storage form, and back.
  *  su3_pack:   src is FP64 AoS; dst is the `precision` form of a
  *              (SU3_F32: round to nearest even; SU3_BF16: round to FP32, then
- *              to BF16, each to nearest even; SU3_R12_F32: rows 0 and 1 of
- *              every link rounded to FP32, 192 B per site; SU3_F64: copy).
+ *              to BF16, each to nearest even; SU3_R12_F32 and SU3_R12C_F32:
+ *              rows 0 and 1 of every link rounded to FP32, 192 B per site;
+ *              SU3_R12_F64: rows 0 and 1 kept in FP64, 384 B per site;
+ *              SU3_F64: copy).
  *  su3_unpack: src is the `precision` form; dst is FP64 AoS. Widening is
- *              exact; for SU3_R12_F32 row 2 is rebuilt in FP64 as
- *              conj(row0 x row1) from the widened rows.
- * Both are bit-exact functions of their input (integer-exact conversions).
+ *              exact; for the reconstruct-12 forms row 2 is rebuilt in FP64
+ *              as conj(row0 x row1) from the widened rows, each product and
+ *              difference rounded separately (no fused multiply-add).
+ * Both are bit-exact functions of their input.
  */
 int su3_pack(const void *src_f64_aos, void *dst, int64_t sites, int precision,
              void *stream);

@@ -4,12 +4,24 @@
     from paper_2103_00571_amd import ops
     c = ops.mult_nn(a, b)          # c[s][j] = a[s][j] @ b[j]
 
-The package fails on import when libsu3.so is missing; there is no other
-implementation to fall back to.
+`abi` and `ops` load libsu3.so on first import and raise ImportError when it
+is missing or stale; there is no other implementation to fall back to. The
+`build` submodule compiles the library and never loads it.
 """
 
-from . import abi, ops  # noqa: F401
-from .ops import (SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, SU3MultNN, aos_to_soa,  # noqa: F401
-                  mult_nn, mult_nn_autograd, mult_nn_bwd, mult_nn_soa, pack, soa_to_aos, unpack)
+import importlib
 
-__version__ = "0.1.0"
+__version__ = "0.2.0"
+
+_LAZY = {"abi", "ops"}
+_OPS_NAMES = {"SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32", "SU3_R12C_F32", "SU3_R12_F64", "SU3MultNN",
+              "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_autograd", "mult_nn_bwd", "mult_nn_soa",
+              "aos_to_soa", "soa_to_aos", "pack", "unpack", "stream_copy", "launch_shape", "form_of"}
+
+
+def __getattr__(name):
+    if name in _LAZY:
+        return importlib.import_module("." + name, __name__)
+    if name in _OPS_NAMES:
+        return getattr(importlib.import_module(".ops", __name__), name)
+    raise AttributeError("module %r has no attribute %r" % (__name__, name))

@@ -15,8 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsu3.so")
 
 # su3.h constants
-ABI_VERSION = 1
-SU3_F64, SU3_F32, SU3_BF16, SU3_R12_F32 = 0, 1, 2, 3
+ABI_VERSION = 2
+SU3_F64, SU3_F32, SU3_BF16, SU3_R12_F32, SU3_R12C_F32, SU3_R12_F64 = 0, 1, 2, 3, 4, 5
 SU3_OK = 0
 SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION = -1, -2, -3, -4
 SU3_ERR_OVERLAP, SU3_ERR_WORKSPACE, SU3_ERR_HIP = -5, -6, -7
@@ -28,6 +28,9 @@ SIGNATURES = {
     "su3_status_string": ([_I], ctypes.c_char_p),
     "su3_mult_nn": ([_P, _P, _P, _I64, _I, _P], _I),
     "su3_mult_nn_soa": ([_P, _P, _P, _I64, _I, _P], _I),
+    "su3_mult_na": ([_P, _P, _P, _I64, _I, _P], _I),
+    "su3_mult_an": ([_P, _P, _P, _I64, _I, _P], _I),
+    "su3_mat_vec": ([_P, _P, _P, _I64, _I, _P], _I),
     "su3_aos_to_soa": ([_P, _P, _I64, _I, _P], _I),
     "su3_soa_to_aos": ([_P, _P, _I64, _I, _P], _I),
     "su3_pack": ([_P, _P, _I64, _I, _P], _I),
@@ -85,6 +88,18 @@ def su3_status_string(status: int) -> str:
 
 def su3_mult_nn(a: int, b: int, c: int, sites: int, precision: int, stream: int) -> int:
     return lib.su3_mult_nn(a, b, c, sites, precision, stream)
+
+
+def su3_mult_na(a: int, b: int, c: int, sites: int, precision: int, stream: int) -> int:
+    return lib.su3_mult_na(a, b, c, sites, precision, stream)
+
+
+def su3_mult_an(a: int, b: int, c: int, sites: int, precision: int, stream: int) -> int:
+    return lib.su3_mult_an(a, b, c, sites, precision, stream)
+
+
+def su3_mat_vec(a: int, v: int, w: int, sites: int, precision: int, stream: int) -> int:
+    return lib.su3_mat_vec(a, v, w, sites, precision, stream)
 
 
 def su3_mult_nn_soa(a: int, b: int, c: int, sites: int, precision: int, stream: int) -> int:

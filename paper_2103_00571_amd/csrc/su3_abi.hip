@@ -20,6 +20,8 @@ bool form_of(int precision, Form &f)
     case SU3_F32: f = {288, 288, 288, 4}; return true;
     case SU3_BF16: f = {144, 144, 288, 4}; return true;
     case SU3_R12_F32: f = {192, 288, 288, 4}; return true;
+    case SU3_R12C_F32: f = {192, 192, 288, 4}; return true;
+    case SU3_R12_F64: f = {384, 576, 576, 8}; return true;
     default: return false;
     }
 }
@@ -121,6 +123,52 @@ int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites, int pr
     if (!grid_fits(fwd_soa_grid(sites), kBlock))
         return SU3_ERR_SIZE;
     return status_of(launch_fwd_soa(a, b, c, sites, precision == SU3_F64 ? 16 : 8, (hipStream_t)stream));
+}
+
+int su3_mult_na(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
+{
+    if (precision != SU3_F64 && precision != SU3_F32)
+        return SU3_ERR_PRECISION;
+    Form f;
+    int st = check_lattice(a, b, c, sites, precision, f);
+    if (st != SU3_OK || sites == 0)
+        return st;
+    if (!grid_fits(fwd_aos_grid(precision, sites), aos_block_threads()))
+        return SU3_ERR_SIZE;
+    return status_of(launch_fwd_na(a, b, c, sites, precision, (hipStream_t)stream));
+}
+
+int su3_mult_an(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
+{
+    if (precision != SU3_F64 && precision != SU3_F32)
+        return SU3_ERR_PRECISION;
+    Form f;
+    int st = check_lattice(a, b, c, sites, precision, f);
+    if (st != SU3_OK || sites == 0)
+        return st;
+    if (!grid_fits(fwd_an_grid(precision, sites), aos_block_threads()))
+        return SU3_ERR_SIZE;
+    return status_of(launch_fwd_an(a, b, c, sites, precision, (hipStream_t)stream));
+}
+
+int su3_mat_vec(const void *a, const void *v, void *w, int64_t sites, int precision, void *stream)
+{
+    if (precision != SU3_F64 && precision != SU3_F32)
+        return SU3_ERR_PRECISION;
+    if (sites < 0 || sites > kMaxSites)
+        return SU3_ERR_SIZE;
+    if (sites == 0)
+        return SU3_OK;
+    if (!a || !v || !w)
+        return SU3_ERR_NULL;
+    if (!aligned(a, 16) || !aligned(w, 16) || !aligned(v, 8))
+        return SU3_ERR_ALIGN;
+    const int64_t es = precision == SU3_F64 ? 16 : 8;   // bytes per complex
+    if (overlap(w, sites * 12 * es, a, sites * 36 * es) || overlap(w, sites * 12 * es, v, sites * 3 * es))
+        return SU3_ERR_OVERLAP;
+    if (!grid_fits(mat_vec_grid(precision, sites), 64))
+        return SU3_ERR_SIZE;
+    return status_of(launch_mat_vec(a, v, w, sites, precision, (hipStream_t)stream));
 }
 
 static int transform(const void *src, void *dst, int64_t sites, int precision, bool to_soa, void *stream)

@@ -41,6 +41,15 @@
 #ifndef SU3_WAVES_R12
 #define SU3_WAVES_R12 6
 #endif
+#ifndef SU3_WAVES_R12C
+#define SU3_WAVES_R12C 12
+#endif
+#ifndef SU3_WAVES_R12F64
+#define SU3_WAVES_R12F64 6
+#endif
+#ifndef SU3_WAVES_AN
+#define SU3_WAVES_AN 4
+#endif
 #ifndef SU3_WAVES_SOA_F64
 #define SU3_WAVES_SOA_F64 12
 #endif
@@ -242,6 +251,118 @@ struct FormR12 {
     }
 };
 
+// Reconstruct-12 in and out (FP32): unit = one link, rows 0-1 in (48 B)
+// and rows 0-1 of the product out (48 B). Rows 0-1 of a*b depend only on
+// rows 0-1 of a, so no row is rebuilt.
+struct FormR12C {
+    static constexpr int kIn = 3, kOut = 3, kUnitsPerSite = 4, kWavesPerCU = SU3_WAVES_R12C;
+    typedef float B;
+    typedef Link<float> Coef;
+    __device__ static void load(const B *b, int pos, Coef &m) { load_link(b, pos, m); }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &m, u4 (&o)[kOut])
+    {
+        float x[12], y[12];
+        unpack_chunks<3>(v, x);
+        row_times(x, m.r, m.i, y);
+        row_times(x + 6, m.r, m.i, y + 6);
+        pack_chunks<3>(y, o);
+    }
+};
+
+// Third row of a link in SU(3) from its first two, FP64.
+__device__ __forceinline__ void recon_row2_f64(const double *r0, const double *r1, double *r2)
+{
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int p = (l + 1) % 3, q = (l + 2) % 3;
+        double xr = r0[2 * p] * r1[2 * q];
+        xr = __builtin_fma(-r0[2 * p + 1], r1[2 * q + 1], xr);
+        xr = __builtin_fma(-r0[2 * q], r1[2 * p], xr);
+        xr = __builtin_fma(r0[2 * q + 1], r1[2 * p + 1], xr);
+        double xi = r0[2 * p] * r1[2 * q + 1];
+        xi = __builtin_fma(r0[2 * p + 1], r1[2 * q], xi);
+        xi = __builtin_fma(-r0[2 * q], r1[2 * p + 1], xi);
+        xi = __builtin_fma(-r0[2 * q + 1], r1[2 * p], xi);
+        r2[2 * l] = xr;
+        r2[2 * l + 1] = -xi;
+    }
+}
+
+// Reconstruct-12 in FP64: unit = one link, rows 0-1 in FP64 (96 B), the full
+// FP64 product out (144 B).
+struct FormR12F64 {
+    static constexpr int kIn = 6, kOut = 9, kUnitsPerSite = 4, kWavesPerCU = SU3_WAVES_R12F64;
+    typedef double B;
+    typedef Link<double> Coef;
+    __device__ static void load(const B *b, int pos, Coef &m) { load_link(b, pos, m); }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &m, u4 (&o)[kOut])
+    {
+        double x[18], y[18];
+        unpack_chunks<6>(v, x);
+        recon_row2_f64(x, x + 6, x + 12);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            row_times(x + 6 * k, m.r, m.i, y + 6 * k);
+        pack_chunks<9>(y, o);
+    }
+};
+
+// c = a^H b for one link held as 9 complex values x (row-major):
+// c(k, l) = sum_m conj(a(m, k)) b(m, l).
+template <typename S>
+__device__ __forceinline__ void link_an(const S *x, const Link<S> &m, S *y)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            S re = 0, im = 0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                cmac(re, im, x[2 * (3 * q + k)], -x[2 * (3 * q + k) + 1], m.r[3 * q + l], m.i[3 * q + l]);
+            y[2 * (3 * k + l)] = re;
+            y[2 * (3 * k + l) + 1] = im;
+        }
+}
+
+// a^H b, FP64: unit = one link (the whole link is needed for its columns),
+// 144 B in and out.
+struct FormAnF64 {
+    static constexpr int kIn = 9, kOut = 9, kUnitsPerSite = 4, kWavesPerCU = SU3_WAVES_AN;
+    typedef double B;
+    typedef Link<double> Coef;
+    __device__ static void load(const B *b, int pos, Coef &m) { load_link(b, pos, m); }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &m, u4 (&o)[kOut])
+    {
+        double x[18], y[18];
+        unpack_chunks<9>(v, x);
+        link_an(x, m, y);
+        pack_chunks<9>(y, o);
+    }
+};
+
+// a^H b, FP32: unit = links 2w, 2w+1 (144 B in and out).
+struct FormAnF32 {
+    static constexpr int kIn = 9, kOut = 9, kUnitsPerSite = 2, kWavesPerCU = SU3_WAVES_AN;
+    typedef float B;
+    struct Coef {
+        Link<float> m[2];
+    };
+    __device__ static void load(const B *b, int pos, Coef &c)
+    {
+        load_link(b, 2 * pos, c.m[0]);
+        load_link(b, 2 * pos + 1, c.m[1]);
+    }
+    __device__ static void apply(const u4 (&v)[kIn], const Coef &c, u4 (&o)[kOut])
+    {
+        float x[36], y[36];
+        unpack_chunks<9>(v, x);
+        link_an(x, c.m[0], y);
+        link_an(x + 18, c.m[1], y + 18);
+        pack_chunks<9>(y, o);
+    }
+};
+
 // Order LDS traffic between the lanes of one wavefront (LDS operations of a
 // wavefront execute in order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_sync()
@@ -260,7 +381,9 @@ __device__ __forceinline__ void wave_sync()
 // than a persistent grid-stride loop (which lets workgroups drift apart in
 // memory). The four b links are staged once per workgroup in LDS and each
 // lane reads the coefficients of its own unit position from there.
-template <class F>
+// kConjB: stage b[j]^H instead of b[j] (the a b^H product; the kernel is
+// otherwise the same).
+template <class F, bool kConjB = false>
 __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, const typename F::B *__restrict__ b,
                                                   u4 *__restrict__ c, int64_t units)
 {
@@ -284,7 +407,16 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 #pragma unroll
     for (int r = 0; r < kBPer; ++r) {
         const int q = threadIdx.x + r * kAosBlock;
-        bv[r] = q < 72 ? b[q] : typename F::B(0);
+        if (!kConjB) {
+            bv[r] = q < 72 ? b[q] : typename F::B(0);
+        } else {
+            // scalar q = 2*(9j + 3m + l) + part of b^H is part of b[j](l, m),
+            // negated for the imaginary part
+            const int e = q >> 1, part = q & 1;
+            const int j = e / 9, m = (e % 9) / 3, l = e % 3;
+            const typename F::B x = q < 72 ? b[2 * (9 * j + 3 * l + m) + part] : typename F::B(0);
+            bv[r] = part ? -x : x;
+        }
     }
     // Branch-free tile loads: a chunk past the end of the lattice (ragged last
     // tile, or a wavefront with no tile) re-reads the last chunk and is never
@@ -412,19 +544,27 @@ int64_t fwd_aos_grid(int precision, int64_t sites)
     case 0: return aos_grid<FormF64>(sites);
     case 1: return aos_grid<FormF32>(sites);
     case 2: return aos_grid<FormBF16>(sites);
-    default: return aos_grid<FormR12>(sites);
+    case 3: return aos_grid<FormR12>(sites);
+    case 4: return aos_grid<FormR12C>(sites);
+    default: return aos_grid<FormR12F64>(sites);
     }
+}
+
+int64_t fwd_an_grid(int precision, int64_t sites)
+{
+    return precision == 0 ? aos_grid<FormAnF64>(sites) : aos_grid<FormAnF32>(sites);
 }
 
 int64_t fwd_soa_grid(int64_t sites) { return (sites + kBlock - 1) / kBlock; }
 
-template <class F>
+template <class F, bool kConjB = false>
 static hipError_t launch_aos(const void *a, const void *b, void *c, int64_t sites, hipStream_t s)
 {
     static std::atomic<int> pad_cache[kMaxDevices];
-    const size_t pad = occupancy_pad(reinterpret_cast<const void *>(fwd_aos<F>), F::kWavesPerCU, kAosBlock, pad_cache);
-    return launch_k(fwd_aos<F>, dim3((unsigned)aos_grid<F>(sites)), dim3(kAosBlock), s, pad, (const u4 *)a,
-                    (const typename F::B *)b, (u4 *)c, sites * F::kUnitsPerSite);
+    const size_t pad =
+        occupancy_pad(reinterpret_cast<const void *>(fwd_aos<F, kConjB>), F::kWavesPerCU, kAosBlock, pad_cache);
+    return launch_k(fwd_aos<F, kConjB>, dim3((unsigned)aos_grid<F>(sites)), dim3(kAosBlock), s, pad,
+                    (const u4 *)a, (const typename F::B *)b, (u4 *)c, sites * F::kUnitsPerSite);
 }
 
 hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s)
@@ -433,8 +573,24 @@ hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, 
     case 0: return launch_aos<FormF64>(a, b, c, sites, s);
     case 1: return launch_aos<FormF32>(a, b, c, sites, s);
     case 2: return launch_aos<FormBF16>(a, b, c, sites, s);
-    default: return launch_aos<FormR12>(a, b, c, sites, s);
+    case 3: return launch_aos<FormR12>(a, b, c, sites, s);
+    case 4: return launch_aos<FormR12C>(a, b, c, sites, s);
+    default: return launch_aos<FormR12F64>(a, b, c, sites, s);
     }
+}
+
+hipError_t launch_fwd_na(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s)
+{
+    if (precision == 0)
+        return launch_aos<FormF64, true>(a, b, c, sites, s);
+    return launch_aos<FormF32, true>(a, b, c, sites, s);
+}
+
+hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s)
+{
+    if (precision == 0)
+        return launch_aos<FormAnF64>(a, b, c, sites, s);
+    return launch_aos<FormAnF32>(a, b, c, sites, s);
 }
 
 hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s)

@@ -87,6 +87,13 @@ size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> 
 int64_t fwd_aos_grid(int precision, int64_t sites);
 int64_t fwd_soa_grid(int64_t sites);
 hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s);
+// The a b^H and a^H b products (FP64 = 0, FP32 = 1).
+int64_t fwd_an_grid(int precision, int64_t sites);
+hipError_t launch_fwd_na(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s);
+hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s);
+// Matrix times colour vector, w[s][j] = a[s][j] v[s] (FP64 = 0, FP32 = 1).
+int64_t mat_vec_grid(int precision, int64_t sites);
+hipError_t launch_mat_vec(const void *a, const void *v, void *w, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s);
 int aos_block_threads();
 // Layout and storage-form conversions.

@@ -78,6 +78,17 @@ __global__ __launch_bounds__(kBlock) void pack_r12(const d2 *__restrict__ src, f
     }
 }
 
+// FP64 links -> rows 0 and 1 kept in FP64 (reconstruct-12 in FP64).
+__global__ __launch_bounds__(kBlock) void pack_r12_f64(const d2 *__restrict__ src, d2 *__restrict__ dst,
+                                                       int64_t links)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            dst[6 * t + q] = src[9 * t + q];
+    }
+}
+
 // ------------------------------------------------------------ unpack
 __global__ __launch_bounds__(kBlock) void unpack_f32(const f2 *__restrict__ src, d2 *__restrict__ dst, int64_t n)
 {
@@ -98,19 +109,20 @@ __global__ __launch_bounds__(kBlock) void unpack_bf16(const uint32_t *__restrict
     }
 }
 
-// Rows 0-1 in FP32 -> full FP64 link; row 2 = conj(row0 x row1) evaluated in
+// Rows 0-1 (FP32 or FP64) -> full FP64 link; row 2 = conj(row0 x row1) evaluated in
 // FP64 without contraction, each product and difference rounded on its own,
 // in the order (r0_p r1_q) - (r0_q r1_p) with each complex product formed as
 // (re*re - im*im, re*im + im*re). The result is then a fixed function of the
 // stored rows, independent of compiler contraction choices.
-__global__ __launch_bounds__(kBlock) void unpack_r12(const f2 *__restrict__ src, d2 *__restrict__ dst, int64_t links)
+template <typename V>
+__global__ __launch_bounds__(kBlock) void unpack_r12(const V *__restrict__ src, d2 *__restrict__ dst, int64_t links)
 {
 #pragma clang fp contract(off)
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
         double r[12];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const f2 v = src[6 * t + q];
+            const V v = src[6 * t + q];
             r[2 * q] = (double)v.x;
             r[2 * q + 1] = (double)v.y;
             d2 o = {r[2 * q], r[2 * q + 1]};
@@ -174,7 +186,9 @@ hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStre
                     (const u4 *)src, (u4 *)dst, n);
 }
 
-// precision codes as in su3.h: 0 F64, 1 F32, 2 BF16, 3 R12_F32
+// precision codes as in su3.h: 0 F64, 1 F32, 2 BF16, 3 R12_F32 (rows 0-1 FP32
+// in, full FP32 out), 4 R12C_F32 (rows 0-1 FP32 in and out), 5 R12_F64 (rows
+// 0-1 FP64 in, full FP64 out). Codes 3 and 4 share the storage of a.
 hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s)
 {
     const int64_t elems = sites * 36, links = sites * 4;
@@ -185,7 +199,11 @@ hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision,
         return launch_k(pack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const d2 *)src,
                         (uint32_t *)dst, elems);
     case 3:
+    case 4:
         return launch_k(pack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (f2 *)dst, links);
+    case 5:
+        return launch_k(pack_r12_f64, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst,
+                        links);
     default:
         return launch_stream_copy(src, dst, elems * 16, s);
     }
@@ -202,7 +220,11 @@ hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precisio
         return launch_k(unpack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const uint32_t *)src,
                         (d2 *)dst, elems);
     case 3:
-        return launch_k(unpack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const f2 *)src, (d2 *)dst,
+    case 4:
+        return launch_k(unpack_r12<f2>, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const f2 *)src, (d2 *)dst,
+                        links);
+    case 5:
+        return launch_k(unpack_r12<d2>, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst,
                         links);
     default:
         return launch_stream_copy(src, dst, elems * 16, s);

@@ -9,8 +9,12 @@ Tensor forms (site-major "AoS", one row per site, see include/su3.h):
     SU3_F32       complex64  (N, 4, 3, 3)        complex64 (4,3,3)   like a
     SU3_BF16      bfloat16   (N, 4, 3, 3, 2)     complex64 (4,3,3)   like a
     SU3_R12_F32   complex64  (N, 4, 2, 3)        complex64 (4,3,3)   complex64 (N,4,3,3)
+    SU3_R12C_F32  complex64  (N, 4, 2, 3)        complex64 (4,3,3)   complex64 (N,4,2,3)
+    SU3_R12_F64   complex128 (N, 4, 2, 3)        complex128 (4,3,3)  complex128 (N,4,3,3)
 
-SoA tensors are (4, 3, 3, N) in complex128 or complex64.
+SU3_R12C_F32 stores a exactly like SU3_R12_F32; pass form=SU3_R12C_F32 to
+keep the product compressed. SoA tensors are (4, 3, 3, N) in complex128 or
+complex64.
 """
 
 from __future__ import annotations
@@ -18,16 +22,16 @@ from __future__ import annotations
 import torch
 
 from . import abi
-from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, check
+from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, SU3_R12_F64, SU3_R12C_F32, check
 
 __all__ = [
-    "SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32",
-    "form_of", "mult_nn", "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack",
+    "SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32", "SU3_R12C_F32", "SU3_R12_F64",
+    "form_of", "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack",
     "mult_nn_bwd", "stream_copy", "SU3MultNN", "mult_nn_autograd", "launch_shape",
 ]
 
 _B_DTYPE = {SU3_F64: torch.complex128, SU3_F32: torch.complex64, SU3_BF16: torch.complex64,
-            SU3_R12_F32: torch.complex64}
+            SU3_R12_F32: torch.complex64, SU3_R12C_F32: torch.complex64, SU3_R12_F64: torch.complex128}
 
 
 def _stream(t: torch.Tensor) -> int:
@@ -55,16 +59,22 @@ def form_of(a: torch.Tensor) -> int:
         return SU3_BF16
     if a.dtype == torch.complex64 and a.dim() == 4 and tuple(a.shape[1:]) == (4, 2, 3):
         return SU3_R12_F32
+    if a.dtype == torch.complex128 and a.dim() == 4 and tuple(a.shape[1:]) == (4, 2, 3):
+        return SU3_R12_F64
     raise ValueError("not a lattice tensor: dtype %s shape %s" % (a.dtype, tuple(a.shape)))
 
 
 def _c_shape(form: int, sites: int) -> tuple:
-    return (sites, 4, 3, 3, 2) if form == SU3_BF16 else (sites, 4, 3, 3)
+    if form == SU3_BF16:
+        return (sites, 4, 3, 3, 2)
+    if form == SU3_R12C_F32:
+        return (sites, 4, 2, 3)
+    return (sites, 4, 3, 3)
 
 
 def _c_dtype(form: int) -> torch.dtype:
     return {SU3_F64: torch.complex128, SU3_F32: torch.complex64, SU3_BF16: torch.bfloat16,
-            SU3_R12_F32: torch.complex64}[form]
+            SU3_R12_F32: torch.complex64, SU3_R12C_F32: torch.complex64, SU3_R12_F64: torch.complex128}[form]
 
 
 def _check_b(b: torch.Tensor, form: int) -> None:
@@ -72,9 +82,15 @@ def _check_b(b: torch.Tensor, form: int) -> None:
         raise ValueError("b must be %s of shape (4, 3, 3) for this form" % _B_DTYPE[form])
 
 
-def mult_nn(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """c[s][j] = a[s][j] @ b[j] on the site-major layout (any form)."""
-    form = form_of(a)
+def mult_nn(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+            form: int | None = None) -> torch.Tensor:
+    """c[s][j] = a[s][j] @ b[j] on the site-major layout (any form; the form
+    is taken from a unless given, which selects SU3_R12C_F32)."""
+    inferred = form_of(a)
+    if form is None:
+        form = inferred
+    elif not (form == inferred or (form == SU3_R12C_F32 and inferred == SU3_R12_F32)):
+        raise ValueError("a is not stored in form %d" % form)
     _check_b(b, form)
     sites = a.shape[0]
     if out is None:
@@ -85,6 +101,49 @@ def mult_nn(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -
     with torch.cuda.device(a.device):
         check(abi.su3_mult_nn(a.data_ptr(), b.data_ptr(), out.data_ptr(), sites, form, _stream(a)),
               "su3_mult_nn")
+    return out
+
+
+def _mult_other(fn, name: str, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None) -> torch.Tensor:
+    form = form_of(a)
+    if form not in (SU3_F64, SU3_F32):
+        raise ValueError("%s exists for FP64 and FP32 links" % name)
+    _check_b(b, form)
+    if out is None:
+        out = torch.empty_like(a)
+    elif out.dtype != a.dtype or out.shape != a.shape:
+        raise ValueError("out has the wrong dtype or shape")
+    _need_gpu(a, b, out)
+    with torch.cuda.device(a.device):
+        check(fn(a.data_ptr(), b.data_ptr(), out.data_ptr(), a.shape[0], form, _stream(a)), name)
+    return out
+
+
+def mult_na(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """c[s][j] = a[s][j] @ b[j]^H (FP64, FP32)."""
+    return _mult_other(abi.su3_mult_na, "su3_mult_na", a, b, out)
+
+
+def mult_an(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """c[s][j] = a[s][j]^H @ b[j] (FP64, FP32)."""
+    return _mult_other(abi.su3_mult_an, "su3_mult_an", a, b, out)
+
+
+def mat_vec(a: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """w[s][j] = a[s][j] @ v[s]: a (N, 4, 3, 3), v (N, 3), w (N, 4, 3), FP64 or FP32."""
+    form = form_of(a)
+    if form not in (SU3_F64, SU3_F32):
+        raise ValueError("mat_vec exists for FP64 and FP32 links")
+    sites = a.shape[0]
+    if v.dtype != a.dtype or tuple(v.shape) != (sites, 3):
+        raise ValueError("v must be (sites, 3) of a's dtype")
+    if out is None:
+        out = torch.empty((sites, 4, 3), dtype=a.dtype, device=a.device)
+    elif out.dtype != a.dtype or tuple(out.shape) != (sites, 4, 3):
+        raise ValueError("out has the wrong dtype or shape")
+    _need_gpu(a, v, out)
+    with torch.cuda.device(a.device):
+        check(abi.su3_mat_vec(a.data_ptr(), v.data_ptr(), out.data_ptr(), sites, form, _stream(a)), "su3_mat_vec")
     return out
 
 
@@ -139,8 +198,10 @@ def _packed_spec(form: int, sites: int) -> tuple[tuple, torch.dtype]:
         return (sites, 4, 3, 3), torch.complex64
     if form == SU3_BF16:
         return (sites, 4, 3, 3, 2), torch.bfloat16
-    if form == SU3_R12_F32:
+    if form in (SU3_R12_F32, SU3_R12C_F32):
         return (sites, 4, 2, 3), torch.complex64
+    if form == SU3_R12_F64:
+        return (sites, 4, 2, 3), torch.complex128
     raise ValueError("unknown form %r" % form)
 
 
@@ -158,8 +219,9 @@ def pack(a64: torch.Tensor, form: int) -> torch.Tensor:
 
 def unpack(x: torch.Tensor, form: int | None = None) -> torch.Tensor:
     """Storage form -> FP64 AoS links (R12 rebuilds row 2 in FP64)."""
-    form = form_of(x) if form is None else form
-    if form_of(x) != form:
+    inferred = form_of(x)
+    form = inferred if form is None else form
+    if not (form == inferred or (form == SU3_R12C_F32 and inferred == SU3_R12_F32)):
         raise ValueError("tensor is not in form %d" % form)
     out = torch.empty((x.shape[0], 4, 3, 3), dtype=torch.complex128, device=x.device)
     _need_gpu(x, out)

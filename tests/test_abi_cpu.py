@@ -49,10 +49,13 @@ def test_status_strings(abi):
     assert "unknown" in abi.su3_status_string(42)
 
 
-A, B, C = 1 << 20, 1 << 30, 1 << 40   # 16-byte aligned fake device addresses, far apart
+# 16-byte aligned fake device addresses, far apart. Every call below must be
+# rejected (or be a no-op for zero sites) before any HIP call: none of them
+# may pass validation, or it would launch a kernel on these addresses.
+A, B, C = 1 << 20, 1 << 30, 1 << 40
 
 
-@pytest.mark.parametrize("form", [0, 1, 2, 3])
+@pytest.mark.parametrize("form", [0, 1, 2, 3, 4, 5])
 def test_mult_nn_validation(abi, form):
     f = abi.su3_mult_nn
     assert f(A, B, C, 0, form, None) == abi.SU3_OK            # nothing to do: no launch
@@ -67,8 +70,34 @@ def test_mult_nn_validation(abi, form):
     assert f(A, B, A, 5, form, None) == abi.SU3_ERR_OVERLAP            # in place
     assert f(A, B, A + 16 * 7, 5, form, None) == abi.SU3_ERR_OVERLAP   # partial overlap
     assert f(A, C + 32, C, 5, form, None) == abi.SU3_ERR_OVERLAP       # c covers b
-    assert f(A, B, C, 5, 4, None) == abi.SU3_ERR_PRECISION
+    assert f(A, B, C, 5, 6, None) == abi.SU3_ERR_PRECISION
     assert f(A, B, C, 5, -1, None) == abi.SU3_ERR_PRECISION
+
+
+@pytest.mark.parametrize("name", ["su3_mult_na", "su3_mult_an"])
+def test_na_an_validation(abi, name):
+    f = getattr(abi, name)
+    for form in (2, 3, 4, 5, 6):
+        assert f(A, B, C, 5, form, None) == abi.SU3_ERR_PRECISION
+    for form in (0, 1):
+        assert f(A, B, C, 0, form, None) == abi.SU3_OK
+        assert f(A, B, C, -2, form, None) == abi.SU3_ERR_SIZE
+        assert f(0, B, C, 5, form, None) == abi.SU3_ERR_NULL
+        assert f(A + 4, B, C, 5, form, None) == abi.SU3_ERR_ALIGN
+        assert f(A, B, A + 32, 5, form, None) == abi.SU3_ERR_OVERLAP
+
+
+def test_mat_vec_validation(abi):
+    f = abi.su3_mat_vec
+    V = 1 << 35
+    assert f(A, V, C, 0, 0, None) == abi.SU3_OK
+    assert f(A, V, C, 5, 2, None) == abi.SU3_ERR_PRECISION
+    assert f(A, V, C, -1, 0, None) == abi.SU3_ERR_SIZE
+    assert f(A, 0, C, 5, 0, None) == abi.SU3_ERR_NULL
+    assert f(A, V + 4, C, 5, 1, None) == abi.SU3_ERR_ALIGN      # v needs 8 bytes
+    assert f(A, V, C + 8, 5, 0, None) == abi.SU3_ERR_ALIGN      # w needs 16
+    assert f(A, V, A + 64, 5, 0, None) == abi.SU3_ERR_OVERLAP   # w over a
+    assert f(A, V, V + 16, 5, 1, None) == abi.SU3_ERR_OVERLAP   # w over v
 
 
 def test_soa_transform_pack_validation(abi):
@@ -84,6 +113,7 @@ def test_soa_transform_pack_validation(abi):
         assert f(0, C, 5, 0, None) == abi.SU3_ERR_NULL
     for f in (abi.su3_pack, abi.su3_unpack):
         assert f(A, C, -3, 1, None) == abi.SU3_ERR_SIZE
+        assert f(A, C, 5, 6, None) == abi.SU3_ERR_PRECISION
         assert f(A, C, 5, 7, None) == abi.SU3_ERR_PRECISION
         assert f(A, A + 64, 5, 1, None) == abi.SU3_ERR_OVERLAP
         assert f(A, 0, 5, 1, None) == abi.SU3_ERR_NULL

@@ -1,0 +1,178 @@
+"""GPU parity of the products beyond the paper's a b: reconstruct-12 in and
+out (FP32), reconstruct-12 in FP64, a b^H, a^H b, and the matrix x colour
+vector product, against the oracle. Tolerances: FP64 1e-13, FP32 5e-6,
+reconstruct-12 FP32 1e-5 (max abs component error vs the FP64 oracle on the
+unrounded inputs)."""
+
+import numpy as np
+import pytest
+import torch
+
+import latgen
+from _gpu import all_finite, guards_intact, poisoned, sample_sites, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TAILS = [1, 2, 3, 63, 65, 257, 4097, 65537]
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2103_00571_amd import ops
+    return ops
+
+
+def _case(sites, seed):
+    return latgen.random_lattice(sites, seed=seed), latgen.random_b(seed=seed + 1)
+
+
+# ------------------------------------------------------- reconstruct-12, FP32 out compressed
+
+@pytest.mark.parametrize("sites", TAILS)
+def test_r12c_product(O, ops, sites):
+    say("r12c sites=%d" % sites)
+    a, b = _case(sites, sites)
+    a12 = ops.pack(to_dev(a), ops.SU3_R12C_F32)
+    b32 = O.round_f32(b)
+    out, whole = poisoned((sites, 4, 2, 3), torch.complex64)
+    ops.mult_nn(a12, to_dev(b32), out=out, form=ops.SU3_R12C_F32)
+    torch.cuda.synchronize()
+    assert guards_intact(whole) and all_finite(out)
+    c = out.cpu().numpy()
+    # rows 0-1 of the product equal those of the full reconstruct-12 emulator
+    emu = O.mult_nn_r12(a12.cpu().numpy(), b32)
+    assert O.max_abs_diff(c, np.ascontiguousarray(emu[:, :, :2, :])) <= 2e-6
+    ref = O.mult_nn(a, b)
+    assert O.max_abs_diff(c.astype(np.complex128), np.ascontiguousarray(ref[:, :, :2, :])) <= 1e-5
+    # the compressed product unpacks (row 2 rebuilt) to the full product
+    full = ops.unpack(out, ops.SU3_R12C_F32).cpu().numpy()
+    assert O.max_abs_diff(full, ref) <= 1e-5
+
+
+def test_r12c_identity_exact(O, ops):
+    say("r12c identity")
+    a = latgen.random_lattice(5000, seed=9)
+    a12 = ops.pack(to_dev(a), ops.SU3_R12C_F32)
+    c = ops.mult_nn(a12, to_dev(latgen.identity_b().astype(np.complex64)), form=ops.SU3_R12C_F32)
+    assert torch.equal(torch.view_as_real(c), torch.view_as_real(a12))
+
+
+# ------------------------------------------------------- reconstruct-12, FP64
+
+@pytest.mark.parametrize("sites", TAILS)
+def test_r12_f64_product(O, ops, sites):
+    say("r12 f64 sites=%d" % sites)
+    a, b = _case(sites, sites + 7)
+    a12 = ops.pack(to_dev(a), ops.SU3_R12_F64)
+    assert np.array_equal(a12.cpu().numpy(), a[:, :, :2, :])
+    out, whole = poisoned((sites, 4, 3, 3), torch.complex128)
+    ops.mult_nn(a12, to_dev(b), out=out)
+    torch.cuda.synchronize()
+    assert guards_intact(whole) and all_finite(out)
+    c = out.cpu().numpy()
+    assert O.max_abs_diff(c, O.mult_nn_r12_f64(a12.cpu().numpy(), b)) <= 1e-13
+    assert O.max_abs_diff(c, O.mult_nn(a, b)) <= 1e-13
+
+
+def test_r12_f64_unpack_bit_exact(O, ops):
+    """unpack rebuilds row 2 with the oracle's operation order and no fused
+    multiply-add, so it equals the oracle's rebuild bit for bit."""
+    say("r12 f64 unpack")
+    a = latgen.random_lattice(20000, seed=13)
+    a12 = ops.pack(to_dev(a), ops.SU3_R12_F64)
+    u = ops.unpack(a12).cpu().numpy()
+    ref = O.mult_nn_r12_f64(a12.cpu().numpy(), latgen.identity_b())
+    assert np.array_equal(u.view(np.uint64), ref.view(np.uint64))
+
+
+# ------------------------------------------------------- a b^H and a^H b
+
+@pytest.mark.parametrize("sites", TAILS)
+@pytest.mark.parametrize("op", ["na", "an"])
+def test_na_an(O, ops, op, sites):
+    say("%s sites=%d" % (op, sites))
+    a, b = _case(sites, sites + 21)
+    fn = ops.mult_na if op == "na" else ops.mult_an
+    ref = (O.mult_na if op == "na" else O.mult_an)(a, b)
+    out, whole = poisoned((sites, 4, 3, 3), torch.complex128)
+    fn(to_dev(a), to_dev(b), out=out)
+    torch.cuda.synchronize()
+    assert guards_intact(whole) and all_finite(out)
+    assert O.max_abs_diff(out.cpu().numpy(), ref) <= 1e-13
+    out32, whole32 = poisoned((sites, 4, 3, 3), torch.complex64)
+    fn(to_dev(O.round_f32(a)), to_dev(O.round_f32(b)), out=out32)
+    torch.cuda.synchronize()
+    assert guards_intact(whole32) and all_finite(out32)
+    assert O.max_abs_diff(out32.cpu().numpy().astype(np.complex128), ref) <= 5e-6
+
+
+def test_na_an_exact_pins(O, ops):
+    say("na/an exact pins")
+    a = latgen.random_lattice(3000, seed=31)
+    ta = to_dev(a)
+    eye = to_dev(latgen.identity_b())
+    assert np.array_equal(ops.mult_na(ta, eye).cpu().numpy(), a)
+    assert np.array_equal(ops.mult_an(ta, eye).cpu().numpy(), np.conj(np.swapaxes(a, 2, 3)))
+    pb = latgen.permutation_b()
+    assert np.array_equal(ops.mult_na(ta, to_dev(pb)).cpu().numpy(), O.mult_na(a, pb))
+    assert np.array_equal(ops.mult_an(ta, to_dev(pb)).cpu().numpy(), O.mult_an(a, pb))
+
+
+def test_na_an_l32(O, ops):
+    say("na/an L=32")
+    sites = 32 ** 4
+    a, b = _case(sites, 1)
+    ta, tb = to_dev(a), to_dev(b)
+    assert O.max_abs_diff(ops.mult_na(ta, tb).cpu().numpy(), O.mult_na(a, b)) <= 1e-13
+    assert O.max_abs_diff(ops.mult_an(ta, tb).cpu().numpy(), O.mult_an(a, b)) <= 1e-13
+
+
+# ------------------------------------------------------- matrix x colour vector
+
+def _vec(sites, seed):
+    return latgen.complex_normal_lattice(sites, seed=seed)[:, 0, 0, :].copy()
+
+
+@pytest.mark.parametrize("sites", TAILS)
+def test_mat_vec(O, ops, sites):
+    say("mat_vec sites=%d" % sites)
+    a, _ = _case(sites, sites + 41)
+    v = _vec(sites, sites + 43)
+    ref = O.mat_vec(a, v)
+    out, whole = poisoned((sites, 4, 3), torch.complex128)
+    ops.mat_vec(to_dev(a), to_dev(v), out=out)
+    torch.cuda.synchronize()
+    assert guards_intact(whole) and all_finite(out)
+    assert O.max_abs_diff(out.cpu().numpy(), ref) <= 1e-13
+    # FP32: an odd site count leaves the last colour vector straddling a
+    # 16-byte boundary, which the kernel reads as 8-byte words
+    out32, whole32 = poisoned((sites, 4, 3), torch.complex64)
+    ops.mat_vec(to_dev(O.round_f32(a)), to_dev(O.round_f32(v)), out=out32)
+    torch.cuda.synchronize()
+    assert guards_intact(whole32) and all_finite(out32)
+    assert O.max_abs_diff(out32.cpu().numpy().astype(np.complex128), ref) <= 5e-6
+
+
+def test_mat_vec_exact_pins(O, ops):
+    say("mat_vec exact pins")
+    sites = 999
+    v = _vec(sites, 5)
+    eye = np.broadcast_to(np.eye(3, dtype=np.complex128), (sites, 4, 3, 3)).copy()
+    w = ops.mat_vec(to_dev(eye), to_dev(v)).cpu().numpy()
+    assert np.array_equal(w, np.broadcast_to(v[:, None, :], (sites, 4, 3)))
+    a = latgen.index_coded(sites)
+    e0 = np.zeros((sites, 3), dtype=np.complex128)
+    e0[:, 1] = 1.0
+    w = ops.mat_vec(to_dev(a), to_dev(e0)).cpu().numpy()   # picks column 1 of every link
+    assert np.array_equal(w, a[:, :, :, 1])
+
+
+def test_mat_vec_l48_sampled(O, ops):
+    sites = 48 ** 4
+    say("mat_vec L=48 sampled")
+    a, _ = _case(sites, 1)
+    v = _vec(sites, 3)
+    w = ops.mat_vec(to_dev(a), to_dev(v))
+    idx = sample_sites(sites, 20000, seed=7)
+    got = w[torch.from_numpy(idx).to(w.device)].cpu().numpy()
+    assert O.max_abs_diff(got, O.mat_vec(a[idx], v[idx])) <= 1e-13
