@@ -41,6 +41,7 @@
 #ifndef SU3_WAVES_R12
 #define SU3_WAVES_R12 6
 #endif
+// (R12C: 3 KiB of loads per wavefront, like FP64; R12F64: 6 KiB; AN: 9 KiB.)
 #ifndef SU3_WAVES_R12C
 #define SU3_WAVES_R12C 12
 #endif
