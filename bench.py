@@ -110,7 +110,7 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
     ap.add_argument("--forms", default="f64,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,bwd")
