@@ -34,6 +34,18 @@ FLOP_PER_SITE = 864            # paper's count: 4 x 27 x (4 mul + 4 add)
 BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "f32": 576, "bf16": 288, "r12": 480,
                   "r12c": 384, "r12f64": 960, "na": 1152, "an": 1152, "matvec": 816}
 BWD_BYTES_PER_SITE = {"f64": 3 * 576, "f32": 3 * 288}   # a, dC read; dA written
+# The paper's own figures for this kernel, on its hardware (context, not a
+# target): 864 flop per site, sites/s = GF/s * 1e9 / 864.
+PAPER_CONTEXT = {
+    "xeon_2x_clx8280_56c_fp32_L32_best": {"gflop_s": 193.54, "gb_s_padded_site": 143.46, "sites_per_s": 2.24e8,
+                                          "where": "section Performance on Xeon (empty constructors, parallel first touch)"},
+    "xeon_2x_clx8280_56c_fp32_L32_openmp_v1": {"gflop_s": 94.82, "sites_per_s": 1.10e8,
+                                               "where": "section Performance on Xeon (OpenMP versions table, Version 1, 200 iterations)"},
+    "piuma_32_cores_fp64_L32": {"gb_s": 108.0, "vs_32_clx_cores": 1.48,
+                                "where": "section Optimization on PIUMA (simulator)"},
+    "piuma_16_cores_fp64_L32": {"gflop_s": 43.88, "gb_s": 61.42, "sites_per_s": 5.08e7,
+                                "where": "section Optimization on PIUMA (simulator)"},
+}
 KERNEL_SOURCES = ["paper_2103_00571_amd/csrc/su3_fwd.hip", "paper_2103_00571_amd/csrc/su3_internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_aos_f64_L48.json")
 
@@ -293,6 +305,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": results,
+        "paper_context": PAPER_CONTEXT,
         "device": torch.cuda.get_device_name(dev),
     }
     print(json.dumps(line), flush=True)

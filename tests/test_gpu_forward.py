@@ -126,3 +126,47 @@ def test_l48_sampled_parity_and_closure(O, ops):
     assert O.max_abs_diff(c[idx], O.mult_nn(a[idx], b)) <= TOL64
     assert O.unitarity_dev(c) <= 1e-13
     assert O.det_dev(c) <= 1e-13
+
+
+def test_zero_b_gives_zero(ops):
+    """Degenerate b = 0: every product is exactly zero, in every form."""
+    say("fwd zero b")
+    a = latgen.random_lattice(4099, seed=71)
+    ta = to_dev(a)
+    z64 = torch.zeros((4, 3, 3), dtype=torch.complex128, device=dev())
+    z32 = z64.to(torch.complex64)
+    assert torch.count_nonzero(torch.view_as_real(ops.mult_nn(ta, z64))).item() == 0
+    for code in (ops.SU3_F32, ops.SU3_BF16, ops.SU3_R12_F32, ops.SU3_R12C_F32):
+        c = ops.mult_nn(ops.pack(ta, code), z32, form=code)
+        r = c.float() if c.dtype == torch.bfloat16 else torch.view_as_real(c)
+        assert torch.count_nonzero(r).item() == 0
+    c = ops.mult_nn(ops.pack(ta, ops.SU3_R12_F64), z64)
+    assert torch.count_nonzero(torch.view_as_real(c)).item() == 0
+
+
+def test_non_finite_input_stays_in_its_row(O, ops):
+    """A NaN and an infinity in a[s] reach only the output rows that read
+    them; every other output is finite and matches the oracle."""
+    say("fwd non-finite locality")
+    a = latgen.random_lattice(2000, seed=72)
+    b = latgen.random_b(seed=73)
+    a[123, 1, 2, 0] = complex(float("nan"), 0.0)
+    a[1500, 3, 0, 2] = complex(0.0, float("inf"))
+    c = ops.mult_nn(to_dev(a), to_dev(b)).cpu().numpy()
+    bad = ~np.isfinite(c.view(np.float64).reshape(2000, 4, 3, 3, 2)).all(axis=(3, 4))
+    assert set(map(tuple, np.argwhere(bad))) == {(123, 1, 2), (1500, 3, 0)}
+    keep = np.ones(2000, dtype=bool)
+    keep[[123, 1500]] = False
+    ref = O.mult_nn(a[keep], b)
+    assert O.max_abs_diff(c[keep], ref) <= TOL64
+
+
+def test_hand_expanded_2_4_lattice(ops):
+    """The GPU product on a 2^4 lattice against the 3x3 products written out
+    entry by entry (c_kl = a_k0 b_0l + a_k1 b_1l + a_k2 b_2l)."""
+    say("fwd f64 hand-expanded 2^4")
+    from test_oracle_pins import _hand_expanded
+    a = latgen.random_lattice(2 ** 4, seed=131)
+    b = latgen.random_b(seed=132)
+    c = ops.mult_nn(to_dev(a), to_dev(b)).cpu().numpy()
+    assert np.abs(c - _hand_expanded(a, b)).max() <= 1e-15

@@ -406,3 +406,29 @@ def test_paper_sizes_and_flop_count():
     assert 4 * 27 * 8 == g["flop_per_site"]
     assert g["flop_per_site"] / (2 * g["site_bytes_f32"]) == pytest.approx(g["ai_f32"])
     assert g["flop_per_site"] / (2 * g["site_bytes_f64"]) == pytest.approx(g["ai_f64"])
+
+
+def _hand_expanded(a, b):
+    """Every entry written out: c_kl = a_k0 b_0l + a_k1 b_1l + a_k2 b_2l."""
+    c = np.empty_like(a)
+    for s in range(a.shape[0]):
+        for j in range(4):
+            A, B = a[s, j], b[j]
+            c[s, j, 0, 0] = A[0, 0] * B[0, 0] + A[0, 1] * B[1, 0] + A[0, 2] * B[2, 0]
+            c[s, j, 0, 1] = A[0, 0] * B[0, 1] + A[0, 1] * B[1, 1] + A[0, 2] * B[2, 1]
+            c[s, j, 0, 2] = A[0, 0] * B[0, 2] + A[0, 1] * B[1, 2] + A[0, 2] * B[2, 2]
+            c[s, j, 1, 0] = A[1, 0] * B[0, 0] + A[1, 1] * B[1, 0] + A[1, 2] * B[2, 0]
+            c[s, j, 1, 1] = A[1, 0] * B[0, 1] + A[1, 1] * B[1, 1] + A[1, 2] * B[2, 1]
+            c[s, j, 1, 2] = A[1, 0] * B[0, 2] + A[1, 1] * B[1, 2] + A[1, 2] * B[2, 2]
+            c[s, j, 2, 0] = A[2, 0] * B[0, 0] + A[2, 1] * B[1, 0] + A[2, 2] * B[2, 0]
+            c[s, j, 2, 1] = A[2, 0] * B[0, 1] + A[2, 1] * B[1, 1] + A[2, 2] * B[2, 1]
+            c[s, j, 2, 2] = A[2, 0] * B[0, 2] + A[2, 1] * B[1, 2] + A[2, 2] * B[2, 2]
+    return c
+
+
+def test_hand_expanded_2_4_lattice(O):
+    """The 3x3 products written out entry by entry on a 2^4 lattice (16 sites
+    x 4 links) agree with the oracle to 1e-15."""
+    a = latgen.random_lattice(2 ** 4, seed=131)
+    b = latgen.random_b(seed=132)
+    assert O.max_abs_diff(O.mult_nn(a, b), _hand_expanded(a, b)) <= 1e-15
