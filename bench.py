@@ -1,14 +1,15 @@
 """Benchmark of the SU(3) link multiply c[s][j] = a[s][j] b[j] on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--L 48] [--forms f64,soa,f32,bf16,r12,copy,bwd]
+    python bench.py [--steps K] [--warmup W] [--L 48] [--forms f64,shard8,soa,...,copy,bwd]
 
 One step is one pass of the product over the whole lattice. The headline is
 the FP64 site-major (AoS) product on an L=48 lattice (5,308,416 sites, 3.06 GB
 per array): W untimed passes, then K passes timed with HIP events on the
 stream the kernel runs on, bracketed by device synchronisation. `value` is
-sites per second. The other storage forms, the SoA layout, the streaming copy
-over the same footprint (the measured bandwidth reference) and the adjoint
-(L=32) are timed the same way and reported under "forms".
+sites per second. The other storage forms, the SoA layout, one GPU's share of
+the lattice split over 8 GPUs (shard8), the streaming copy over the same
+footprint (the measured bandwidth reference) and the adjoint (L=32) are timed
+the same way and reported under "forms".
 
 Inputs are seeded synthetic Haar SU(3) links (latgen), generated on the host
 and copied to HBM before timing starts. Prints one JSON line.
@@ -125,7 +126,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
-    ap.add_argument("--forms", default="f64,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,bwd")
+    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -176,6 +177,17 @@ def main() -> int:
     ms64 = time_launches(lambda: ops.mult_nn(ta, tb64, out=c64), args.steps, args.warmup, torch)
     record("f64", ms64, BYTES_PER_SITE["f64"], sites)
     outputs["f64"] = c64
+
+    # ---- one GPU's share when the lattice is split over 8 GPUs ----------------
+    # (sites are independent and b is replicated, so a shard is the same kernel
+    # on a contiguous range of sites)
+    if "shard8" in forms and sites >= 8:
+        ns = sites // 8
+        xs, ys = ta[:ns], torch.empty_like(ta[:ns])
+        ms = time_launches(lambda: ops.mult_nn(xs, tb64, out=ys), args.steps, args.warmup, torch)
+        record("shard8", ms, BYTES_PER_SITE["f64"], ns)
+        results["shard8"]["sites"] = ns
+        del ys
 
     # ---- streaming copy over the same footprint (measured bandwidth) -------
     if "copy" in forms:

@@ -197,9 +197,9 @@ int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da,
                     size_t ws_bytes, void *stream);
 
 /*
- * Measurement aid: device-to-device copy of `bytes` bytes with 16-byte
- * loads and nontemporal 16-byte stores over a grid-stride loop, the same
- * access pattern as the link multiply without the arithmetic. Used to
+ * Measurement aid: device-to-device copy of `bytes` bytes, one 16-byte
+ * nontemporal load and store per thread over a grid that covers the buffer
+ * once, the streaming pattern of the link multiply without the arithmetic. Used to
  * measure the HBM bandwidth the multiply is compared against. bytes must be
  * a multiple of 16; src and dst 16-byte aligned and non-overlapping.
  */

@@ -237,7 +237,7 @@ size_t su3_mult_nn_bwd_workspace_bytes(int64_t sites, int precision)
         return 0;
     if (sites <= 0 || sites > kMaxSites)
         return 0;
-    return (size_t)bwd_groups(sites, precision) * 72 * sizeof(double);
+    return (size_t)bwd_workspace_doubles(sites, precision) * sizeof(double);
 }
 
 int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, double *db_f64, int64_t sites,
@@ -247,7 +247,7 @@ int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, doub
         return SU3_ERR_PRECISION;
     Form f;
     form_of(precision, f);
-    if (sites < 0 || sites > kMaxSites)
+    if (sites < 0 || sites > kMaxSites || !grid_fits(bwd_groups(sites, precision), bwd_block_threads()))
         return SU3_ERR_SIZE;
     if (!db_f64)
         return SU3_ERR_NULL;

@@ -17,23 +17,30 @@
 // position within the wavefront (lanes in increasing order), then per link
 // over the workgroup's wavefronts and the link's three rows. Each workgroup
 // writes one 4x3x3 complex FP64 partial, component-major.
-// Stage 2 (bwd_reduce): one workgroup per real component of dB adds the
-// partials in a fixed strided order and a fixed binary tree.
-// The number of workgroups depends only on the number of sites, so the
-// rounding sequence, and every bit of dB, is the same on every run and every
-// device. No atomics.
+// Stage 2 reduces the partials of each of the 72 real components in two
+// fixed-order levels: bwd_chunk_sums adds runs of kChunk consecutive partials
+// (8 per thread, then a binary tree), bwd_reduce adds the run sums (a strided
+// loop, then a binary tree). Both levels keep every load of a thread in
+// flight at once, so stage 2 costs a few microseconds at any lattice size.
+// The number of workgroups of every stage depends only on the number of sites
+// and the form, so the rounding sequence, and every bit of dB, is the same on
+// every run and every device. No atomics.
 #include "su3_internal.hpp"
 
 namespace su3 {
 
 constexpr int kBwdWaves = 3;                 // wavefronts per workgroup
 constexpr int kBwdThreads = 64 * kBwdWaves;
-#ifndef SU3_BWD_TILES
-#define SU3_BWD_TILES 8
+// Tiles per wavefront and resident wavefronts per CU for stage 1 (0: as many
+// as fit), measured at L=32 over 1, 2, 4, 8 tiles and 9 or 12 wavefronts.
+// More tiles per wavefront amortise the closing reduction; fewer shorten the
+// drain at the end of the grid.
+#ifndef SU3_BWD_TILES_F64
+#define SU3_BWD_TILES_F64 4
 #endif
-constexpr int kTiles = SU3_BWD_TILES;        // tiles per wavefront
-// Resident wavefronts per CU for stage 1 (0: as many as fit). 9 wavefronts
-// (54 KiB of tile loads in flight per CU) measured best at L=32.
+#ifndef SU3_BWD_TILES_F32
+#define SU3_BWD_TILES_F32 4
+#endif
 #ifndef SU3_BWD_WAVES_F64
 #define SU3_BWD_WAVES_F64 9
 #endif
@@ -44,13 +51,17 @@ constexpr int kTiles = SU3_BWD_TILES;        // tiles per wavefront
 // FP64: unit = one row (3 complex, 48 B); 12 units per site.
 struct BwdF64 {
     typedef double S;
-    static constexpr int kRows = 1, kUnitsPerSite = 12;
+    static constexpr int kRows = 1, kUnitsPerSite = 12, kTiles = SU3_BWD_TILES_F64;
 };
 // FP32: unit = two rows (6 complex float, 48 B); 6 units per site.
 struct BwdF32 {
     typedef float S;
-    static constexpr int kRows = 2, kUnitsPerSite = 6;
+    static constexpr int kRows = 2, kUnitsPerSite = 6, kTiles = SU3_BWD_TILES_F32;
 };
+
+// Stage 2, first level: partials per workgroup.
+constexpr int kChunkLoads = 8;
+constexpr int64_t kChunk = (int64_t)kBlock * kChunkLoads;
 
 // Order LDS traffic between the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync_bwd()
@@ -71,6 +82,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     constexpr int R = F::kRows;
     constexpr int NV = 18 * R;                // accumulator doubles per lane
     constexpr int P = F::kUnitsPerSite;
+    constexpr int kTiles = F::kTiles;
     constexpr int kStageBytes = 2 * 3 * 64 * 16;     // a and dC tiles
     constexpr int kRedBytes = 64 * (NV + 1) * 8;     // lane vectors, padded rows
     constexpr int kBytes = kStageBytes > kRedBytes ? kStageBytes : kRedBytes;
@@ -192,14 +204,31 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     // row sums: output o = 18*r + e for site row r = 0..11. The lane at unit
     // position w holds rows R*w .. R*w+R-1; the lanes at position w are
     // (w - base) mod P and every P-th lane after it, added in increasing order.
+    // Every load of a lane is issued before the first add (fixed trip counts;
+    // a lane index past 63 reads lane 63 and adds an exact zero instead).
     const int base = (int)((t0 * 64) % P);
-    for (int o2 = lane; o2 < 12 * 18; o2 += 64) {
-        const int r = o2 / 18, e = o2 % 18;
-        const int w = r / R, v = 18 * (r % R) + e;
-        double sum = 0.0;
-        for (int l = ((w - base) % P + P) % P; l < 64; l += P)
-            sum += red[l * (NV + 1) + v];
-        rowsum[wv][o2] = sum;
+    constexpr int kLanesPerPos = (64 + P - 1) / P;    // 6 (FP64) or 11 (FP32)
+    constexpr int kRowOut = 12 * 18;
+#pragma unroll
+    for (int it = 0; it < (kRowOut + 63) / 64; ++it) {
+        const int o2 = lane + 64 * it;
+        if (o2 < kRowOut) {
+            const int r = o2 / 18, e = o2 % 18;
+            const int w = r / R, v = 18 * (r % R) + e;
+            const int l0 = ((w - base) % P + P) % P;
+            double x[kLanesPerPos];
+#pragma unroll
+            for (int i = 0; i < kLanesPerPos; ++i) {
+                const int l = l0 + P * i;
+                const double y = red[(l < 64 ? l : 63) * (NV + 1) + v];
+                x[i] = l < 64 ? y : 0.0;
+            }
+            double sum = x[0];
+#pragma unroll
+            for (int i = 1; i < kLanesPerPos; ++i)
+                sum += x[i];
+            rowsum[wv][o2] = sum;
+        }
     }
     __syncthreads();
     // workgroup partial of component q = 18*j + e: wavefronts in order, then
@@ -214,7 +243,44 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     }
 }
 
+// Binary tree over red[0 .. kBlock) in a fixed order; the sum ends in red[0].
+__device__ __forceinline__ void block_tree(double *red)
+{
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+}
+
+// grid = (chunks, 72): workgroup (c, q) adds partials c*kChunk .. c*kChunk +
+// kChunk - 1 of component q (thread t takes t, t + kBlock, ... in order, then
+// the tree) and writes run sum ws2[q * chunks + c].
+__global__ __launch_bounds__(kBlock) void bwd_chunk_sums(const double *__restrict__ ws, double *__restrict__ ws2,
+                                                         int64_t groups, int64_t chunks)
+{
+    __shared__ double red[kBlock];
+    const int64_t c = blockIdx.x;
+    const double *src = ws + (int64_t)blockIdx.y * groups;
+    double v[kChunkLoads];
+#pragma unroll
+    for (int i = 0; i < kChunkLoads; ++i) {
+        const int64_t g = c * kChunk + (int64_t)kBlock * i + threadIdx.x;
+        v[i] = g < groups ? src[g] : 0.0;
+    }
+    double sum = v[0];
+#pragma unroll
+    for (int i = 1; i < kChunkLoads; ++i)
+        sum += v[i];
+    red[threadIdx.x] = sum;
+    block_tree(red);
+    if (threadIdx.x == 0)
+        ws2[(int64_t)blockIdx.y * chunks + c] = red[0];
+}
+
 // grid = 72 workgroups, one per real component of dB; ws is component-major
+// with `groups` values per component
 __global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ ws, double *__restrict__ db,
                                                      int64_t groups)
 {
@@ -224,30 +290,36 @@ __global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ 
     for (int64_t g = threadIdx.x; g < groups; g += kBlock)
         sum += ws[(int64_t)q * groups + g];
     red[threadIdx.x] = sum;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
+    block_tree(red);
     if (threadIdx.x == 0)
         db[q] = red[0];
 }
 
-// Workgroups of stage 1 for `sites` (a function of the size only).
+// Workgroups of stage 1 for `sites` (a function of the size and form only).
 int64_t bwd_groups(int64_t sites, int precision)
 {
     const int64_t units = sites * (precision == 0 ? BwdF64::kUnitsPerSite : BwdF32::kUnitsPerSite);
     const int64_t tiles = (units + 63) / 64;
-    const int64_t per = (int64_t)kBwdWaves * kTiles;
+    const int64_t per = (int64_t)kBwdWaves * (precision == 0 ? BwdF64::kTiles : BwdF32::kTiles);
     return (tiles + per - 1) / per;
 }
+
+static int64_t bwd_chunks(int64_t groups) { return (groups + kChunk - 1) / kChunk; }
+
+int64_t bwd_workspace_doubles(int64_t sites, int precision)
+{
+    const int64_t groups = bwd_groups(sites, precision);
+    return 72 * (groups + bwd_chunks(groups));
+}
+
+int bwd_block_threads() { return kBwdThreads; }
 
 hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
                       int precision, double *ws, hipStream_t s)
 {
     static std::atomic<int> pad64[kMaxDevices], pad32[kMaxDevices];
-    const int64_t groups = bwd_groups(sites, precision);
+    const int64_t groups = bwd_groups(sites, precision), chunks = bwd_chunks(groups);
+    double *ws2 = ws + 72 * groups;
     hipError_t e;
     if (precision == 0) {
         const size_t pad =
@@ -262,7 +334,11 @@ hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, do
     }
     if (e != hipSuccess)
         return e;
-    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)ws, db, groups);
+    e = launch_k(bwd_chunk_sums, dim3((unsigned)chunks, 72), dim3(kBlock), s, 0, (const double *)ws, ws2, groups,
+                 chunks);
+    if (e != hipSuccess)
+        return e;
+    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)ws2, db, chunks);
 }
 
 // An empty lattice has dB = 0: the second stage over zero partials writes

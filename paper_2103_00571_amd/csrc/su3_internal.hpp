@@ -102,8 +102,11 @@ hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision,
 hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
 // Adjoint: stage 1 writes per-workgroup partial sums of db into ws (72 x
-// bwd_groups doubles, component-major), stage 2 reduces them in a fixed order.
+// bwd_groups doubles, component-major), stage 2 reduces them in a fixed order
+// through run sums stored after them; bwd_workspace_doubles is the total.
 int64_t bwd_groups(int64_t sites, int precision);
+int64_t bwd_workspace_doubles(int64_t sites, int precision);
+int bwd_block_threads();
 hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
                       int precision, double *ws, hipStream_t s);
 hipError_t launch_bwd_zero(double *db, hipStream_t s);
