@@ -32,7 +32,7 @@ namespace su3 {
 constexpr int kBwdWaves = 3;                 // wavefronts per workgroup
 constexpr int kBwdThreads = 64 * kBwdWaves;
 // Tiles per wavefront and resident wavefronts per CU for stage 1 (0: as many
-// as fit), measured at L=32 over 1, 2, 4, 8 tiles and 9 or 12 wavefronts.
+// as fit), measured at L=32 over 1, 2, 4, 8 tiles and 6, 9 or 12 wavefronts.
 // More tiles per wavefront amortise the closing reduction; fewer shorten the
 // drain at the end of the grid.
 #ifndef SU3_BWD_TILES_F64
@@ -45,7 +45,7 @@ constexpr int kBwdThreads = 64 * kBwdWaves;
 #define SU3_BWD_WAVES_F64 9
 #endif
 #ifndef SU3_BWD_WAVES_F32
-#define SU3_BWD_WAVES_F32 9
+#define SU3_BWD_WAVES_F32 12
 #endif
 
 // FP64: unit = one row (3 complex, 48 B); 12 units per site.
@@ -118,26 +118,36 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     for (int v = 0; v < NV; ++v)
         acc[v] = 0.0;
 
+    // Tile loads: chunk indices past the end re-read the last chunk (in
+    // bounds; those lanes store nothing and add nothing). The loads of the
+    // next tile are issued as soon as the current tile sits in LDS, so they
+    // are in flight while the current tile is computed and stored.
+    u4 va[3], vg[3];
+    auto load_tile = [&](int64_t t) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int64_t g = t * 64 * 3 + lane + 64 * i;
+            const int64_t gc = g < nchunks ? g : nchunks - 1;
+            vg[i] = ld_stream(dc + gc);
+            va[i] = ld_stream(a + gc);
+        }
+    };
+    if (t0 * 64 < units)
+        load_tile(t0);
     for (int k = 0; k < kTiles; ++k) {
         const int64_t t = t0 + (int64_t)kBwdWaves * k;
         if (t * 64 >= units)
             break;                                   // wave-uniform
         const bool whole = (t + 1) * 64 <= units;
         const int64_t g0 = t * 64 * 3 + lane;
-        u4 va[3], vg[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int64_t g = g0 + 64 * i;
-            const int64_t gc = g < nchunks ? g : nchunks - 1;   // in bounds; unused past the end
-            vg[i] = ld_stream(dc + gc);
-            va[i] = ld_stream(a + gc);
-        }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             stage[64 * i + lane] = vg[i];
             stage[192 + 64 * i + lane] = va[i];
         }
         wave_sync_bwd();
+        if (k + 1 < kTiles && (t + kBwdWaves) * 64 < units)
+            load_tile(t + kBwdWaves);
         S g[6 * R], x[6 * R];   // interleaved re/im of the unit's R rows
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
