@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     constexpr int P = F::kUnitsPerSite;
     constexpr int kTiles = F::kTiles;
     constexpr int kStageBytes = 2 * 3 * 64 * 16;     // a and dC tiles
-    constexpr int kRedBytes = 64 * (NV + 1) * 8;     // lane vectors, padded rows
+    constexpr int kRedBytes = 64 * 19 * 8;           // one row's 18 accumulators per lane, padded
     constexpr int kBytes = kStageBytes > kRedBytes ? kStageBytes : kRedBytes;
     // per-wavefront scratch: tile staging in the loop, reduction after it
     __shared__ __attribute__((aligned(16))) char scratch[kBwdWaves][kBytes];
@@ -206,39 +206,43 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     }
 
     // ---- fixed-order reduction --------------------------------------------
-    // lane vectors -> LDS (row stride NV + 1 doubles)
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        red[lane * (NV + 1) + v] = acc[v];
-    wave_sync_bwd();
-    // row sums: output o = 18*r + e for site row r = 0..11. The lane at unit
-    // position w holds rows R*w .. R*w+R-1; the lanes at position w are
-    // (w - base) mod P and every P-th lane after it, added in increasing order.
-    // Every load of a lane is issued before the first add (fixed trip counts;
-    // a lane index past 63 reads lane 63 and adds an exact zero instead).
+    // One pass per row h of the unit: the lanes' 18 accumulators of row h go
+    // to LDS (row stride 19 doubles), then the row sums of the site rows
+    // r = R*w + h (w = unit position 0..P-1) are formed: output 18*r + e adds
+    // the lanes at position w, (w - base) mod P and every P-th lane after
+    // it, in increasing order. Every load of a lane is issued before the
+    // first add (fixed trip counts; a lane index past 63 reads lane 63 and
+    // adds an exact zero instead).
     const int base = (int)((t0 * 64) % P);
     constexpr int kLanesPerPos = (64 + P - 1) / P;    // 6 (FP64) or 11 (FP32)
-    constexpr int kRowOut = 12 * 18;
+    constexpr int kPassOut = P * 18;                  // outputs per pass: 216 / R
 #pragma unroll
-    for (int it = 0; it < (kRowOut + 63) / 64; ++it) {
-        const int o2 = lane + 64 * it;
-        if (o2 < kRowOut) {
-            const int r = o2 / 18, e = o2 % 18;
-            const int w = r / R, v = 18 * (r % R) + e;
-            const int l0 = ((w - base) % P + P) % P;
-            double x[kLanesPerPos];
+    for (int h = 0; h < R; ++h) {
 #pragma unroll
-            for (int i = 0; i < kLanesPerPos; ++i) {
-                const int l = l0 + P * i;
-                const double y = red[(l < 64 ? l : 63) * (NV + 1) + v];
-                x[i] = l < 64 ? y : 0.0;
+        for (int v = 0; v < 18; ++v)
+            red[lane * 19 + v] = acc[18 * h + v];
+        wave_sync_bwd();
+#pragma unroll
+        for (int it = 0; it < (kPassOut + 63) / 64; ++it) {
+            const int o3 = lane + 64 * it;
+            if (o3 < kPassOut) {
+                const int w = o3 / 18, e = o3 % 18;
+                const int l0 = ((w - base) % P + P) % P;
+                double x[kLanesPerPos];
+#pragma unroll
+                for (int i = 0; i < kLanesPerPos; ++i) {
+                    const int l = l0 + P * i;
+                    const double y = red[(l < 64 ? l : 63) * 19 + e];
+                    x[i] = l < 64 ? y : 0.0;
+                }
+                double sum = x[0];
+#pragma unroll
+                for (int i = 1; i < kLanesPerPos; ++i)
+                    sum += x[i];
+                rowsum[wv][18 * (R * w + h) + e] = sum;
             }
-            double sum = x[0];
-#pragma unroll
-            for (int i = 1; i < kLanesPerPos; ++i)
-                sum += x[i];
-            rowsum[wv][o2] = sum;
         }
+        wave_sync_bwd();
     }
     __syncthreads();
     // workgroup partial of component q = 18*j + e: wavefronts in order, then
