@@ -176,3 +176,45 @@ def test_mat_vec_l48_sampled(O, ops):
     idx = sample_sites(sites, 20000, seed=7)
     got = w[torch.from_numpy(idx).to(w.device)].cpu().numpy()
     assert O.max_abs_diff(got, O.mat_vec(a[idx], v[idx])) <= 1e-13
+
+
+def test_l48_products_sampled(O, ops):
+    """L=48 (5,308,416 sites), the inputs and launch configuration the
+    benchmark times: a b^H, a^H b, reconstruct-12 in and out, reconstruct-12
+    in FP64, the SoA product, and the FP64 product on one GPU's share of the
+    lattice split over 8 GPUs (the first 663,552 sites), each on 20,000
+    sampled sites against the oracle."""
+    sites = 48 ** 4
+    a, b = _case(sites, 1)
+    ta, tb = to_dev(a), to_dev(b)
+    idx = sample_sites(sites, 20000, seed=11)
+    tidx = torch.from_numpy(idx).to(ta.device)
+
+    def sampled(c):
+        return c[tidx].cpu().numpy().astype(np.complex128 if c.dtype == torch.complex128 else np.complex64)
+
+    say("L=48 a b^H")
+    assert O.max_abs_diff(sampled(ops.mult_na(ta, tb)), O.mult_na(a[idx], b)) <= 1e-13
+    say("L=48 a^H b")
+    assert O.max_abs_diff(sampled(ops.mult_an(ta, tb)), O.mult_an(a[idx], b)) <= 1e-13
+    ref = O.mult_nn(a[idx], b)
+    say("L=48 reconstruct-12 FP64")
+    assert O.max_abs_diff(sampled(ops.mult_nn(ops.pack(ta, ops.SU3_R12_F64), tb)), ref) <= 1e-13
+    say("L=48 reconstruct-12 in and out")
+    b32 = to_dev(O.round_f32(b))
+    c12 = ops.mult_nn(ops.pack(ta, ops.SU3_R12C_F32), b32, form=ops.SU3_R12C_F32)
+    got = sampled(c12).astype(np.complex128)
+    del c12
+    assert O.max_abs_diff(got, np.ascontiguousarray(ref[:, :, :2, :])) <= 1e-5
+    say("L=48 SoA")
+    csoa = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(ta), tb))
+    got = sampled(csoa)
+    del csoa
+    assert O.max_abs_diff(got, ref) <= 1e-13
+    say("L=48 / 8 share")
+    ns = sites // 8
+    cs = ops.mult_nn(ta[:ns], tb)
+    sidx = idx[idx < ns]
+    assert sidx.size > 1000
+    got = cs[torch.from_numpy(sidx).to(cs.device)].cpu().numpy()
+    assert O.max_abs_diff(got, O.mult_nn(a[sidx], b)) <= 1e-13
