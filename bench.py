@@ -115,8 +115,20 @@ def cpu_baseline_leg(a, b, sample_idx, seconds: float):
     ref = O.mult_nn(a[sample_idx], b)
     rec = {"value": rate, "unit": "sites/s", "cores": 1, "kind": "oracle",
            "sample": "first %d sites of the L=48 lattice, FP64 AoS, %d passes in %.1f s, single thread"
-                     % (sample.shape[0], passes, el)}
+                     % (sample.shape[0], passes, el),
+           "gb_s": rate * 1152 / 1e9, "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
     return rec, ref, O
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main() -> int:
