@@ -47,6 +47,11 @@ def _need_gpu(*ts: torch.Tensor) -> None:
             raise ValueError("all tensors must be on one device")
         if not t.is_contiguous():
             raise ValueError("tensors must be contiguous")
+        if t.is_conj() or t.is_neg():
+            # a lazy conjugate or negative view shares the memory of its base,
+            # which holds the unconjugated values
+            raise ValueError("tensors must not be lazy conjugate or negative views; call .resolve_conj() "
+                             "and .resolve_neg() first")
 
 
 def form_of(a: torch.Tensor) -> int:
@@ -282,7 +287,9 @@ class SU3MultNN(torch.autograd.Function):
     @staticmethod
     def backward(ctx, dc):
         a, b = ctx.saved_tensors
-        da, db = mult_nn_bwd(a, b, dc.contiguous())
+        # autograd may hand over a lazy conjugate view (after a .conj() in
+        # the graph); the kernels need the values themselves
+        da, db = mult_nn_bwd(a, b, dc.resolve_conj().resolve_neg().contiguous())
         return da, db.to(b.dtype)
 
 

@@ -131,3 +131,18 @@ def test_autograd_f32_dtype(ops):
     c = ops.SU3MultNN.apply(ta, tb)
     (torch.conj(to_dev(dc.astype(np.complex64))) * c).real.sum().backward()
     assert ta.grad.dtype == torch.complex64 and tb.grad.dtype == torch.complex64
+
+
+def test_autograd_through_conjugate(O, ops):
+    """A .conj() after the product makes autograd hand backward a lazy
+    conjugate view of the upstream gradient. For L = Re sum conj(C) w, which
+    equals Re sum conj(w) C, the gradients are the adjoint with dC = w."""
+    say("bwd autograd through conj")
+    a, b, w = _case(4099, seed=95)
+    ta = to_dev(a).requires_grad_(True)
+    tb = to_dev(b).requires_grad_(True)
+    c = ops.SU3MultNN.apply(ta, tb)
+    (c.conj() * to_dev(w)).real.sum().backward()
+    da_ref, db_ref = O.mult_nn_bwd(a, b, w)
+    assert O.max_abs_diff(ta.grad.cpu().numpy(), da_ref) <= 1e-13 * max(1.0, np.abs(w).max())
+    assert O.max_abs_diff(tb.grad.cpu().numpy(), db_ref) <= 1e-12 * np.abs(db_ref).max()

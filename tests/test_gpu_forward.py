@@ -170,3 +170,17 @@ def test_hand_expanded_2_4_lattice(ops):
     b = latgen.random_b(seed=132)
     c = ops.mult_nn(to_dev(a), to_dev(b)).cpu().numpy()
     assert np.abs(c - _hand_expanded(a, b)).max() <= 1e-15
+
+
+def test_lazy_conjugate_views_are_rejected(ops):
+    """torch's lazy conjugate view shares memory with unconjugated values:
+    passing it must fail, not silently use the wrong sign."""
+    say("fwd lazy conj view rejected")
+    a = to_dev(latgen.random_lattice(64, seed=91))
+    b = to_dev(latgen.random_b(seed=92))
+    with pytest.raises(ValueError):
+        ops.mult_nn(a.conj(), b)
+    with pytest.raises(ValueError):
+        ops.mult_nn(a, b.conj())
+    c = ops.mult_nn(a.conj().resolve_conj(), b).cpu().numpy()
+    assert np.abs(c - np.matmul(np.conj(a.cpu().numpy()), b.cpu().numpy()[None])).max() <= 1e-13
