@@ -20,6 +20,7 @@ complex64.
 from __future__ import annotations
 
 import torch
+from torch.autograd.function import once_differentiable
 
 from . import abi
 from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, SU3_R12_F64, SU3_R12C_F32, check
@@ -285,12 +286,14 @@ class SU3MultNN(torch.autograd.Function):
         return mult_nn(a, b)
 
     @staticmethod
+    @once_differentiable
     def backward(ctx, dc):
         a, b = ctx.saved_tensors
         # autograd may hand over a lazy conjugate view (after a .conj() in
         # the graph); the kernels need the values themselves
         da, db = mult_nn_bwd(a, b, dc.resolve_conj().resolve_neg().contiguous())
-        return da, db.to(b.dtype)
+        return (da if ctx.needs_input_grad[0] else None,
+                db.to(b.dtype) if ctx.needs_input_grad[1] else None)
 
 
 def mult_nn_autograd(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:

@@ -146,3 +146,20 @@ def test_autograd_through_conjugate(O, ops):
     da_ref, db_ref = O.mult_nn_bwd(a, b, w)
     assert O.max_abs_diff(ta.grad.cpu().numpy(), da_ref) <= 1e-13 * max(1.0, np.abs(w).max())
     assert O.max_abs_diff(tb.grad.cpu().numpy(), db_ref) <= 1e-12 * np.abs(db_ref).max()
+
+
+def test_autograd_one_input(O, ops):
+    """Gradients for only a, or only b, match the adjoint; the other stays None."""
+    say("bwd autograd one input")
+    a, b, w = _case(513, seed=97)
+    da_ref, db_ref = O.mult_nn_bwd(a, b, w)
+    ta = to_dev(a).requires_grad_(True)
+    tb = to_dev(b)
+    (torch.conj(to_dev(w)) * ops.SU3MultNN.apply(ta, tb)).real.sum().backward()
+    assert O.max_abs_diff(ta.grad.cpu().numpy(), da_ref) <= 1e-13 * max(1.0, np.abs(w).max())
+    assert tb.grad is None
+    ta = to_dev(a)
+    tb = to_dev(b).requires_grad_(True)
+    (torch.conj(to_dev(w)) * ops.SU3MultNN.apply(ta, tb)).real.sum().backward()
+    assert O.max_abs_diff(tb.grad.cpu().numpy(), db_ref) <= 1e-12 * np.abs(db_ref).max()
+    assert ta.grad is None
