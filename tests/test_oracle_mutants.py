@@ -61,6 +61,13 @@ MUTANTS = [
      "su3o_recon_row2(L + 6, L, L + 12);"),
     ("matvec_sign", "su3o_mat_vec(", "re += ar * vr - ai * vi;", "re += ar * vr + ai * vi;"),
     ("matvec_wrong_site", "su3o_mat_vec(", "v[2 * (3 * i + m)]", "v[2 * (3 * ((i + 1) % sites) + m)]"),
+    ("matvec_conj_v", "su3o_mat_vec(", "const double vi = v[2 * (3 * i + m) + 1];",
+     "const double vi = -v[2 * (3 * i + m) + 1];"),
+    ("bwd_da_transposed", "su3o_mult_nn_bwd(", "da[ix(s, j, k, m)] = re;\n                    da[ix(s, j, k, m) + 1] = im;",
+     "da[ix(s, j, m, k)] = re;\n                    da[ix(s, j, m, k) + 1] = im;"),
+    ("bwd_db_a_untransposed", "su3o_mult_nn_bwd(", "const double ar = a[ix(s, j, k, m)];\n                        const double ai = -a[ix(s, j, k, m) + 1];",
+     "const double ar = a[ix(s, j, m, k)];\n                        const double ai = -a[ix(s, j, m, k) + 1];"),
+    ("fwd_wrong_row", "su3o_mult_nn(", "a[ix(i, j, k, m)]", "a[ix(i, j, (k + 1) % 3, m)]"),
 ]
 
 
@@ -73,7 +80,7 @@ def _mutate(src: str, func: str, old: str, new: str) -> str:
     return src[:start] + body.replace(old, new) + src[end:]
 
 
-PIN_MODULES = ("test_oracle_pins.py", "test_oracle_next.py")
+PIN_MODULES = ("test_oracle_pins.py", "test_oracle_next.py", "test_oracle_exact.py")
 
 
 def _pins():
