@@ -1,0 +1,122 @@
+"""Exact-arithmetic GPU parity. With integer entries in [-9, 9] every
+operation the kernels perform is exact: FP64 and FP32 products and sums
+(magnitudes far below 2^24), the BF16 form's FP32 product before its final
+rounding, the rebuilt third row of the reconstruct-12 forms, and the FP64
+site sum of dB. So every result must equal exact integer arithmetic bit for
+bit: integer matrix products through the real embedding x + iy ->
+[[x, -y], [y, x]] (numpy int64), rounded to BF16 by torch where the form
+stores BF16. Sizes are drawn at random (hypothesis), ragged included."""
+
+import numpy as np
+import pytest
+import torch
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+from _gpu import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2103_00571_amd import ops
+    return ops
+
+
+def _embed(z):
+    x, y = np.rint(z.real).astype(np.int64), np.rint(z.imag).astype(np.int64)
+    blk = np.stack([np.stack([x, -y], -1), np.stack([y, x], -1)], -2)
+    nd = blk.ndim
+    order = list(range(nd - 4)) + [nd - 4, nd - 2, nd - 3, nd - 1]
+    sh = blk.shape
+    return blk.transpose(order).reshape(*sh[:-4], 2 * sh[-4], 2 * sh[-3])
+
+
+def _unembed(m):
+    return (m[..., 0::2, 0::2] + 1j * m[..., 1::2, 0::2]).astype(np.complex128)
+
+
+def _T(m):
+    return np.swapaxes(m, -1, -2)
+
+
+def _ints(rng, shape):
+    return (rng.integers(-9, 10, size=shape) + 1j * rng.integers(-9, 10, size=shape)).astype(np.complex128)
+
+
+def _cross_row2(a):
+    """conj(row0 x row1) per link, in exact integers."""
+    r0, r1 = a[..., 0, :], a[..., 1, :]
+    x = np.stack([r0[..., 1] * r1[..., 2] - r0[..., 2] * r1[..., 1],
+                  r0[..., 2] * r1[..., 0] - r0[..., 0] * r1[..., 2],
+                  r0[..., 0] * r1[..., 1] - r0[..., 1] * r1[..., 0]], -1)
+    return np.conj(x)
+
+
+def _same(got, want):
+    got = got.detach().cpu()
+    want = torch.from_numpy(np.ascontiguousarray(want)).to(got.dtype)
+    return torch.equal(torch.view_as_real(got), torch.view_as_real(want))
+
+
+def _bf16_same(got, want):
+    want = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(want))).to(torch.float32).to(torch.bfloat16)
+    return torch.equal(got.cpu().view(torch.int16), want.view(torch.int16))
+
+
+SIZES = st.one_of(st.sampled_from([1, 2, 3, 63, 64, 65, 4097]), st.integers(min_value=1, max_value=70000))
+SEEDS = st.integers(min_value=0, max_value=2 ** 32 - 1)
+
+
+@settings(max_examples=12, deadline=None)
+@given(sites=SIZES, seed=SEEDS)
+def test_forward_forms_exact(ops, sites, seed):
+    say("exact forward forms sites=%d seed=%d" % (sites, seed))
+    rng = np.random.default_rng(seed)
+    a, b = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3))
+    A, B = _embed(a), _embed(b)[None]
+    want = _unembed(A @ B)
+    ta, tb = to_dev(a), to_dev(b)
+    tb32 = tb.to(torch.complex64)
+    assert _same(ops.mult_nn(ta, tb), want)
+    assert _same(ops.mult_nn(ops.pack(ta, ops.SU3_F32), tb32), want)
+    assert _bf16_same(ops.mult_nn(ops.pack(ta, ops.SU3_BF16), tb32), want)
+    assert _same(ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(ta), tb)), want)
+    # reconstruct-12: the kernels rebuild row 2 as conj(row0 x row1)
+    a12 = a.copy()
+    a12[:, :, 2, :] = _cross_row2(a)
+    want12 = _unembed(_embed(a12) @ B)
+    assert _same(ops.mult_nn(ops.pack(ta, ops.SU3_R12_F32), tb32), want12)
+    assert _same(ops.mult_nn(ops.pack(ta, ops.SU3_R12_F64), tb), want12)
+    assert _same(ops.mult_nn(ops.pack(ta, ops.SU3_R12C_F32), tb32, form=ops.SU3_R12C_F32), want[:, :, :2, :])
+
+
+@settings(max_examples=12, deadline=None)
+@given(sites=SIZES, seed=SEEDS)
+def test_other_products_exact(ops, sites, seed):
+    say("exact a b^H, a^H b, matrix x vector sites=%d seed=%d" % (sites, seed))
+    rng = np.random.default_rng(seed)
+    a, b, v = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3)), _ints(rng, (sites, 3))
+    A, B = _embed(a), _embed(b)[None]
+    V = _embed(v[:, None, :, None])[:, 0]
+    for dt in (torch.complex128, torch.complex64):
+        ta, tb, tv = to_dev(a).to(dt), to_dev(b).to(dt), to_dev(v).to(dt)
+        assert _same(ops.mult_na(ta, tb), _unembed(A @ _T(B)))
+        assert _same(ops.mult_an(ta, tb), _unembed(_T(A) @ B))
+        assert _same(ops.mat_vec(ta, tv), _unembed(A @ V[:, None])[..., 0])
+
+
+@settings(max_examples=12, deadline=None)
+@given(sites=SIZES, seed=SEEDS)
+def test_adjoint_exact(ops, sites, seed):
+    say("exact adjoint sites=%d seed=%d" % (sites, seed))
+    rng = np.random.default_rng(seed)
+    a, b, dc = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3)), _ints(rng, (sites, 4, 3, 3))
+    A, B, G = _embed(a), _embed(b)[None], _embed(dc)
+    want_da = _unembed(G @ _T(B))
+    want_db = _unembed((_T(A) @ G).sum(axis=0))
+    for dt in (torch.complex128, torch.complex64):
+        da, db = ops.mult_nn_bwd(to_dev(a).to(dt), to_dev(b).to(dt), to_dev(dc).to(dt))
+        assert _same(da, want_da)
+        assert _same(db, want_db)
