@@ -120,3 +120,36 @@ def test_adjoint_exact(ops, sites, seed):
         da, db = ops.mult_nn_bwd(to_dev(a).to(dt), to_dev(b).to(dt), to_dev(dc).to(dt))
         assert _same(da, want_da)
         assert _same(db, want_db)
+
+
+def test_beyond_2_31_chunks(ops):
+    """A lattice of 60,000,000 sites (FP64: 2.16e9 16-byte chunks, 34.6 GB
+    per array), past the range of 32-bit chunk indices: the site-major
+    product, the SoA product and a b^H on integer entries, bit-exact on
+    20,000 sampled sites plus the first and last 64."""
+    sites = 60_000_000
+    assert sites * 36 > 2 ** 31
+    say("exact sites=%d (beyond 2^31 chunks)" % sites)
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(2031)
+    a = torch.view_as_complex(torch.randint(-9, 10, (sites, 4, 3, 3, 2), generator=g, device=dev,
+                                            dtype=torch.float64))
+    rng = np.random.default_rng(2031)
+    b = _ints(rng, (4, 3, 3))
+    tb = to_dev(b)
+    idx = np.unique(np.concatenate([rng.integers(0, sites, 20000), np.arange(64), np.arange(sites - 64, sites)]))
+    tidx = torch.from_numpy(idx).to(dev)
+    A, B = _embed(a[tidx].cpu().numpy()), _embed(b)[None]
+    want = _unembed(A @ B)
+    c = ops.mult_nn(a, tb)
+    assert _same(c[tidx], want)
+    say("  a b^H")
+    ops.mult_na(a, tb, out=c)
+    assert _same(c[tidx], _unembed(A @ _T(B)))
+    del c
+    say("  SoA")
+    sa = ops.aos_to_soa(a)
+    del a
+    sc = ops.mult_nn_soa(sa, tb)
+    del sa
+    assert _same(ops.soa_to_aos(sc)[tidx], want)
