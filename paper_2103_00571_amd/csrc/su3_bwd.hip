@@ -16,10 +16,15 @@
 // At the end the lanes' accumulators are summed in a fixed order: per row
 // position within the wavefront (lanes in increasing order), then per link
 // over the workgroup's wavefronts and the link's three rows. Each workgroup
-// writes one 4x3x3 complex FP64 partial, component-major.
+// writes one 4x3x3 complex FP64 partial. Partials are stored in quads of
+// components: quad u = q / 4 holds, for every workgroup g, the 4 doubles of
+// components 4u .. 4u+3 at 4 (u * groups + g), so each workgroup writes 18
+// whole 32-byte sectors rather than 72 scattered doubles (a scattered
+// 8-byte store costs a whole sector of HBM writes).
 // Stage 2 reduces the partials of each of the 72 real components in two
 // fixed-order levels: bwd_chunk_sums adds runs of kChunk consecutive partials
-// (8 per thread, then a binary tree), bwd_reduce adds the run sums (a strided
+// of a quad's 4 components (8 per thread, then a binary tree per component),
+// bwd_reduce adds the run sums, stored component-major (a strided
 // loop, then a binary tree). Both levels keep every load of a thread in
 // flight at once, so stage 2 costs a few microseconds at any lattice size.
 // The number of workgroups of every stage depends only on the number of sites
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
         for (int w2 = 0; w2 < kBwdWaves; ++w2)
             for (int r = 3 * j; r < 3 * j + 3; ++r)
                 sum += rowsum[w2][18 * r + e];
-        ws[(int64_t)threadIdx.x * groups + blockIdx.x] = sum;
+        ws[4 * ((int64_t)(threadIdx.x >> 2) * groups + blockIdx.x) + (threadIdx.x & 3)] = sum;
     }
 }
 
@@ -268,29 +273,46 @@ __device__ __forceinline__ void block_tree(double *red)
     }
 }
 
-// grid = (chunks, 72): workgroup (c, q) adds partials c*kChunk .. c*kChunk +
-// kChunk - 1 of component q (thread t takes t, t + kBlock, ... in order, then
-// the tree) and writes run sum ws2[q * chunks + c].
+// grid = (chunks, 18): workgroup (c, u) adds partials c*kChunk .. c*kChunk +
+// kChunk - 1 of the 4 components of quad u (thread t takes t, t + kBlock,
+// ... in order, then a tree per component) and writes run sums
+// ws2[q * chunks + c] for q = 4u .. 4u+3.
 __global__ __launch_bounds__(kBlock) void bwd_chunk_sums(const double *__restrict__ ws, double *__restrict__ ws2,
                                                          int64_t groups, int64_t chunks)
 {
-    __shared__ double red[kBlock];
+    __shared__ double red[4][kBlock];
     const int64_t c = blockIdx.x;
-    const double *src = ws + (int64_t)blockIdx.y * groups;
-    double v[kChunkLoads];
+    const d2 *src = reinterpret_cast<const d2 *>(ws + 4 * (int64_t)blockIdx.y * groups);
+    d2 v[kChunkLoads][2];
 #pragma unroll
     for (int i = 0; i < kChunkLoads; ++i) {
         const int64_t g = c * kChunk + (int64_t)kBlock * i + threadIdx.x;
-        v[i] = g < groups ? src[g] : 0.0;
+        const d2 z = {0.0, 0.0};
+        v[i][0] = g < groups ? src[2 * g] : z;
+        v[i][1] = g < groups ? src[2 * g + 1] : z;
     }
-    double sum = v[0];
+    double sum[4] = {v[0][0].x, v[0][0].y, v[0][1].x, v[0][1].y};
 #pragma unroll
-    for (int i = 1; i < kChunkLoads; ++i)
-        sum += v[i];
-    red[threadIdx.x] = sum;
-    block_tree(red);
-    if (threadIdx.x == 0)
-        ws2[(int64_t)blockIdx.y * chunks + c] = red[0];
+    for (int i = 1; i < kChunkLoads; ++i) {
+        sum[0] += v[i][0].x;
+        sum[1] += v[i][0].y;
+        sum[2] += v[i][1].x;
+        sum[3] += v[i][1].y;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        red[e][threadIdx.x] = sum[e];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                red[e][threadIdx.x] += red[e][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4)
+        ws2[(int64_t)(4 * blockIdx.y + threadIdx.x) * chunks + c] = red[threadIdx.x][0];
 }
 
 // grid = 72 workgroups, one per real component of dB; ws is component-major
@@ -348,7 +370,7 @@ hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, do
     }
     if (e != hipSuccess)
         return e;
-    e = launch_k(bwd_chunk_sums, dim3((unsigned)chunks, 72), dim3(kBlock), s, 0, (const double *)ws, ws2, groups,
+    e = launch_k(bwd_chunk_sums, dim3((unsigned)chunks, 18), dim3(kBlock), s, 0, (const double *)ws, ws2, groups,
                  chunks);
     if (e != hipSuccess)
         return e;
