@@ -144,7 +144,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
+        print("bench.py runs on one GPU only: it measures the single-GPU kernel "
               "(sites shard across GPUs with no communication in the forward pass); use --gpus 1",
               file=sys.stderr)
         return 2
