@@ -9,7 +9,8 @@ stream the kernel runs on, bracketed by device synchronisation. `value` is
 sites per second. The other storage forms, the SoA layout, one GPU's share of
 the lattice split over 8 GPUs (shard8), the streaming copy over the same
 footprint (the measured bandwidth reference) and the adjoint (L=32) are timed
-the same way and reported under "forms".
+the same way and reported under "forms", with the streaming ceiling of each
+kernel's access shape (su3_stream_shape, "shapes").
 
 Inputs are seeded synthetic Haar SU(3) links (latgen), generated on the host
 and copied to HBM before timing starts. Prints one JSON line.
@@ -138,7 +139,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
-    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,bwd")
+    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,shapes,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -212,6 +213,39 @@ def main() -> int:
         log("copy  %8.4f ms  %7.1f GB/s (library kernel); torch copy_ %7.1f GB/s"
             % (msc, nb / (msc * 1e-3) / 1e9, nb / (msd * 1e-3) / 1e9))
         del dst
+
+    # ---- ceilings of the kernels' access shapes (su3_stream_shape) ----------
+    # Each shape streams the footprint of the kernel it stands beside with no
+    # arithmetic; the best rate over a sweep of the occupancy cap is that
+    # shape's streaming ceiling on this GPU.
+    if "shapes" in forms:
+        bsites = args.bwd_L ** 4
+        shapes = [((3, 0, 3), 12 * sites // 64, "f64, f32, bf16, r12c, na"),
+                  ((1, 0, 1), 36 * sites // 64, "copy"),
+                  ((3, 3, 3), 12 * bsites // 64, "bwd_f64, bwd_f32"),
+                  ((6, 0, 9), 2 * sites // 64, "r12"),
+                  ((9, 0, 9), 4 * sites // 64, "an")]
+        abytes = ta.view(torch.uint8).reshape(-1)
+        bbytes = c64.view(torch.uint8).reshape(-1)
+        cbytes = torch.empty(max(t * 1024 * sh[2] for sh, t, _ in shapes), dtype=torch.uint8, device=dev)
+        res = {}
+        for (ia, ib, io), tiles, beside in shapes:
+            if tiles * 1024 * max(ia, ib) > abytes.numel():
+                continue
+            A, C = abytes[: tiles * 1024 * ia], cbytes[: tiles * 1024 * io]
+            B = bbytes[: tiles * 1024 * ib] if ib else None
+            nbytes = (ia + ib + io) * tiles * 1024
+            best = None
+            for cap in (0, 32, 24, 16, 12, 11, 10, 9, 8, 6, 4):
+                ms = time_launches(lambda: ops.stream_shape(A, B, C, ia, ib, io, cap), 20, 3, torch)
+                gbs = nbytes / (ms * 1e-3) / 1e9
+                if best is None or gbs > best[0]:
+                    best = (gbs, cap, ms)
+            key = "%d+%d in, %d out" % (ia, ib, io)
+            res[key] = {"gb_s": best[0], "waves_per_cu": best[1], "ms": best[2], "bytes": nbytes, "kernels": beside}
+            log("shape %-14s ceiling %7.1f GB/s (cap %d)  beside %s" % (key, best[0], best[1], beside))
+        results["shapes"] = res
+        del cbytes
 
     # ---- SoA ---------------------------------------------------------------
     if "soa" in forms:
@@ -309,6 +343,10 @@ def main() -> int:
                 "bytes_per_site": BYTES_PER_SITE["f64"], "grid": grid, "block": block}
     if "copy" in results:
         roofline["frac_of_measured_copy"] = achieved / results["copy"]["gb_s"]
+    if "shapes" in results and "3+0 in, 3 out" in results["shapes"]:
+        ceil = results["shapes"]["3+0 in, 3 out"]["gb_s"]
+        roofline["shape_ceiling_gb_s"] = ceil
+        roofline["frac_of_shape_ceiling"] = achieved / ceil
 
     line = {
         "metric": METRIC,

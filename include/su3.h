@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define SU3_ABI_VERSION 2
+#define SU3_ABI_VERSION 3
 
 /* storage form codes */
 enum su3_precision {
@@ -204,6 +204,25 @@ int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da,
  * a multiple of 16; src and dst 16-byte aligned and non-overlapping.
  */
 int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
+/*
+ * Measurement aid: the streaming ceiling of an access shape. Over `tiles`
+ * wavefront tiles, tile w reads in_a 16-byte chunks per lane from a (bytes
+ * w*1024*in_a .. (w+1)*1024*in_a - 1, as in_a whole-wavefront 1 KiB runs),
+ * in_b chunks per lane from b likewise, and writes out chunks per lane to c
+ * (bytes w*1024*out ..), with one 64-thread workgroup per tile and at most
+ * waves_per_cu resident wavefronts per CU (0: no cap, at most 32). The
+ * values written are the XOR of the lane's loaded chunks with the chunk
+ * number added to the first word. The shapes are those of the kernels:
+ * (in_a, in_b, out) = (1, 0, 1) copy; (3, 0, 3) the FP64/FP32/BF16 forward;
+ * (3, 3, 3) the adjoint; (6, 0, 9) reconstruct-12 with full output;
+ * (9, 0, 9) a^H b. Sizes: a holds tiles*1024*in_a bytes, b tiles*1024*in_b
+ * (b may be NULL when in_b is 0), c tiles*1024*out; 16-byte aligned; c must
+ * not overlap a or b. Errors: SU3_ERR_SIZE for another shape, a negative
+ * count or a cap above 32; otherwise as su3_stream_copy.
+ */
+int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
+                     int waves_per_cu, void *stream);
 
 /*
  * Launch shape the library uses for su3_mult_nn on the current device:

@@ -291,4 +291,25 @@ int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream)
     return status_of(launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
 }
 
+int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
+                     int waves_per_cu, void *stream)
+{
+    if (!stream_shape_supported(in_a, in_b, out))
+        return SU3_ERR_SIZE;
+    if (tiles < 0 || waves_per_cu < 0 || waves_per_cu > 32 || tiles > kMaxSites)
+        return SU3_ERR_SIZE;
+    if (tiles == 0)
+        return SU3_OK;
+    if (!a || !c || (in_b > 0 && !b))
+        return SU3_ERR_NULL;
+    if (!aligned(a, 16) || !aligned(c, 16) || (in_b > 0 && !aligned(b, 16)))
+        return SU3_ERR_ALIGN;
+    const int64_t na = tiles * 1024 * in_a, nb = tiles * 1024 * in_b, nc = tiles * 1024 * out;
+    if (overlap(c, nc, a, na) || (in_b > 0 && overlap(c, nc, b, nb)))
+        return SU3_ERR_OVERLAP;
+    if (!grid_fits(tiles, 64))
+        return SU3_ERR_SIZE;
+    return status_of(launch_stream_shape(a, b, c, tiles, in_a, in_b, out, waves_per_cu, (hipStream_t)stream));
+}
+
 } // extern "C"

@@ -505,6 +505,24 @@ __global__ __launch_bounds__(kBlock) void fwd_soa(const V *__restrict__ a, const
 // `kernel` are resident per CU: the CU's LDS divided by the wanted number of
 // workgroups, minus the kernel's static LDS. Cached per device; 0 when no cap
 // is wanted or a query fails.
+size_t occupancy_pad_for(const void *kernel, int waves, int block, int dev)
+{
+    int lds_cu = 0, lds_block = 0;
+    hipFuncAttributes attr;
+    int pad = 0;
+    if (waves > 0 && hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        hipFuncGetAttributes(&attr, kernel) == hipSuccess) {
+        // LDS is allocated in granules; round each workgroup's share down to
+        // 1 KiB so that `blocks` of them fit
+        const int blocks = waves * 64 / block > 0 ? waves * 64 / block : 1;
+        const int want = (lds_cu / blocks) / 1024 * 1024 - (int)attr.sharedSizeBytes;
+        const int room = lds_block - (int)attr.sharedSizeBytes;
+        pad = want > 0 ? (want < room ? want : room) : 0;
+    }
+    return (size_t)pad;
+}
+
 size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> (&cache)[kMaxDevices])
 {
     if (waves <= 0)
@@ -515,19 +533,7 @@ size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> 
     int pad = cache[dev].load(std::memory_order_relaxed);   // pad + 1; 0 = not yet known
     if (pad > 0)
         return (size_t)(pad - 1);
-    int lds_cu = 0, lds_block = 0;
-    hipFuncAttributes attr;
-    pad = 0;
-    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
-        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-        hipFuncGetAttributes(&attr, kernel) == hipSuccess) {
-        // LDS is allocated in granules; round each workgroup's share down to
-        // 1 KiB so that `blocks` of them fit
-        const int blocks = waves * 64 / block > 0 ? waves * 64 / block : 1;
-        const int want = (lds_cu / blocks) / 1024 * 1024 - (int)attr.sharedSizeBytes;
-        const int room = lds_block - (int)attr.sharedSizeBytes;
-        pad = want > 0 ? (want < room ? want : room) : 0;
-    }
+    pad = (int)occupancy_pad_for(kernel, waves, block, dev);
     cache[dev].store(pad + 1, std::memory_order_relaxed);
     return (size_t)pad;
 }

@@ -81,6 +81,8 @@ inline hipError_t launch_k(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream
 // that at most `waves` wavefronts are resident per CU; 0 for no cap. Cached
 // per device in `cache` (entries start at 0).
 size_t occupancy_pad(const void *kernel, int waves, int block, std::atomic<int> (&cache)[kMaxDevices]);
+// The same pad for device `dev`, computed on every call (no cache).
+size_t occupancy_pad_for(const void *kernel, int waves, int block, int dev);
 
 // ---- launchers (each returns hipSuccess or the launch error) --------------
 // Forward products. The grid covers the lattice once; *_grid report it.
@@ -101,8 +103,14 @@ hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_by
 hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+// Streaming probe of an access shape: per wavefront tile, in_a (and in_b)
+// 16-byte chunks per lane read, out chunks per lane written. False for a
+// shape it does not implement.
+bool stream_shape_supported(int in_a, int in_b, int out);
+hipError_t launch_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
+                               int waves_per_cu, hipStream_t s);
 // Adjoint: stage 1 writes per-workgroup partial sums of db into ws (72 x
-// bwd_groups doubles, component-major), stage 2 reduces them in a fixed order
+// bwd_groups doubles, in 32-byte quads of components), stage 2 reduces them in a fixed order
 // through run sums stored after them; bwd_workspace_doubles is the total.
 int64_t bwd_groups(int64_t sites, int precision);
 int64_t bwd_workspace_doubles(int64_t sites, int precision);

@@ -155,6 +155,39 @@ __global__ __launch_bounds__(kCopyBlock) void stream_copy(const u4 *__restrict__
         st_stream(dst + i, ld_stream(src + i));
 }
 
+// Access-shape probe: wavefront w reads chunks w*64*RA + 64 i + lane of a
+// (i < RA) and likewise of b, and writes chunks w*64*W + 64 i + lane of c,
+// the same whole-wavefront 1 KiB runs and per-lane chunk counts as the
+// kernels it stands beside, with no arithmetic beyond folding the loads
+// into the stored values (so that no load is dead).
+template <int RA, int RB, int W>
+__global__ __launch_bounds__(64) void stream_shape(const u4 *__restrict__ a, const u4 *__restrict__ b,
+                                                   u4 *__restrict__ c)
+{
+    const int64_t w = blockIdx.x;
+    const int lane = threadIdx.x;
+    u4 va[RA], vb[RB > 0 ? RB : 1];
+#pragma unroll
+    for (int i = 0; i < RA; ++i)
+        va[i] = ld_stream(a + w * 64 * RA + 64 * i + lane);
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        vb[i] = ld_stream(b + w * 64 * RB + 64 * i + lane);
+    u4 x = va[0];
+#pragma unroll
+    for (int i = 1; i < RA; ++i)
+        x ^= va[i];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        x ^= vb[i];
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        u4 o = x;
+        o.x += (uint32_t)i;
+        st_stream(c + w * 64 * W + 64 * i + lane, o);
+    }
+}
+
 // ------------------------------------------------------------ launchers
 static unsigned grid_for(int64_t items, int64_t per_block)
 {
@@ -184,6 +217,40 @@ hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStre
     const int64_t n = bytes / 16;
     return launch_k(stream_copy, dim3((unsigned)((n + kCopyBlock - 1) / kCopyBlock)), dim3(kCopyBlock), s, 0,
                     (const u4 *)src, (u4 *)dst, n);
+}
+
+bool stream_shape_supported(int in_a, int in_b, int out)
+{
+    return (in_a == 1 && in_b == 0 && out == 1) || (in_a == 3 && in_b == 0 && out == 3) ||
+           (in_a == 3 && in_b == 3 && out == 3) || (in_a == 6 && in_b == 0 && out == 9) ||
+           (in_a == 9 && in_b == 0 && out == 9);
+}
+
+template <int RA, int RB, int W>
+static hipError_t launch_shape_k(const void *a, const void *b, void *c, int64_t tiles, int waves, hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return hipErrorInvalidDevice;
+    const size_t pad = occupancy_pad_for(reinterpret_cast<const void *>(stream_shape<RA, RB, W>), waves, 64, dev);
+    return launch_k(stream_shape<RA, RB, W>, dim3((unsigned)tiles), dim3(64), s, pad, (const u4 *)a, (const u4 *)b,
+                    (u4 *)c);
+}
+
+hipError_t launch_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
+                               int waves_per_cu, hipStream_t s)
+{
+    if (in_a == 1 && in_b == 0 && out == 1)
+        return launch_shape_k<1, 0, 1>(a, b, c, tiles, waves_per_cu, s);
+    if (in_a == 3 && in_b == 0 && out == 3)
+        return launch_shape_k<3, 0, 3>(a, b, c, tiles, waves_per_cu, s);
+    if (in_a == 3 && in_b == 3 && out == 3)
+        return launch_shape_k<3, 3, 3>(a, b, c, tiles, waves_per_cu, s);
+    if (in_a == 6 && in_b == 0 && out == 9)
+        return launch_shape_k<6, 0, 9>(a, b, c, tiles, waves_per_cu, s);
+    if (in_a == 9 && in_b == 0 && out == 9)
+        return launch_shape_k<9, 0, 9>(a, b, c, tiles, waves_per_cu, s);
+    return hipErrorInvalidValue;
 }
 
 // precision codes as in su3.h: 0 F64, 1 F32, 2 BF16, 3 R12_F32 (rows 0-1 FP32

@@ -28,7 +28,7 @@ from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, SU3_R12_F64, SU3_R12C_
 __all__ = [
     "SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32", "SU3_R12C_F32", "SU3_R12_F64",
     "form_of", "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack",
-    "mult_nn_bwd", "stream_copy", "SU3MultNN", "mult_nn_autograd", "launch_shape",
+    "mult_nn_bwd", "stream_copy", "stream_shape", "SU3MultNN", "mult_nn_autograd", "launch_shape",
 ]
 
 _B_DTYPE = {SU3_F64: torch.complex128, SU3_F32: torch.complex64, SU3_BF16: torch.complex64,
@@ -255,6 +255,21 @@ def mult_nn_bwd(a: torch.Tensor, b: torch.Tensor, dc: torch.Tensor) -> tuple[tor
         check(abi.su3_mult_nn_bwd(a.data_ptr(), b.data_ptr(), dc.data_ptr(), da.data_ptr(), db.data_ptr(), sites,
                                   form, ws.data_ptr(), ws.numel(), _stream(a)), "su3_mult_nn_bwd")
     return da, db
+
+
+def stream_shape(a: torch.Tensor, b: torch.Tensor | None, c: torch.Tensor, in_a: int, in_b: int, out: int,
+                 waves_per_cu: int = 0) -> None:
+    """The streaming probe of an access shape (su3_stream_shape) over byte
+    buffers: a holds tiles*1024*in_a bytes, b tiles*1024*in_b, c tiles*1024*out."""
+    tiles = a.numel() * a.element_size() // (1024 * in_a)
+    if (a.numel() * a.element_size() != tiles * 1024 * in_a or c.numel() * c.element_size() != tiles * 1024 * out
+            or (in_b and (b is None or b.numel() * b.element_size() != tiles * 1024 * in_b))):
+        raise ValueError("buffer sizes do not match the shape")
+    ts = (a, c) if not in_b else (a, b, c)
+    _need_gpu(*ts)
+    with torch.cuda.device(a.device):
+        check(abi.su3_stream_shape(a.data_ptr(), b.data_ptr() if in_b else None, c.data_ptr(), tiles, in_a, in_b,
+                                   out, waves_per_cu, _stream(a)), "su3_stream_shape")
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:

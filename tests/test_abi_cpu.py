@@ -151,6 +151,20 @@ def test_stream_copy_validation(abi):
     assert abi.su3_stream_copy(A + 4, C, 64, None) == abi.SU3_ERR_ALIGN
 
 
+def test_stream_shape_validation(abi):
+    f = abi.su3_stream_shape
+    assert f(A, 0, C, 0, 3, 0, 3, 0, None) == abi.SU3_OK                 # nothing to do
+    assert f(A, 0, C, 4, 2, 0, 2, 0, None) == abi.SU3_ERR_SIZE           # not a kernel's shape
+    assert f(A, 0, C, -1, 3, 0, 3, 0, None) == abi.SU3_ERR_SIZE
+    assert f(A, 0, C, 4, 3, 0, 3, 33, None) == abi.SU3_ERR_SIZE
+    assert f(0, 0, C, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_NULL
+    assert f(A, 0, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_NULL           # b needed
+    assert f(A + 8, 0, C, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B + 8, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_ALIGN
+    assert f(A, 0, A + 1024, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_OVERLAP
+    assert f(A, C + 16, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_OVERLAP
+
+
 def test_launch_shape_rejects_before_hip(abi):
     g, b = ctypes.c_int64(), ctypes.c_int()
     assert abi.lib.su3_launch_shape(10, 9, ctypes.byref(g), ctypes.byref(b)) == abi.SU3_ERR_PRECISION

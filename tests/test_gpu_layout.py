@@ -60,3 +60,36 @@ def test_soa_matches_aos_at_l32(O, ops):
     c_soa = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(ta), b))
     d = (torch.view_as_real(c_aos) - torch.view_as_real(c_soa)).abs().max().item()
     assert d <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(1, 0, 1), (3, 0, 3), (3, 3, 3), (6, 0, 9), (9, 0, 9)])
+def test_stream_shape_pattern(ops, shape):
+    """The access-shape probe reads and writes exactly the chunks it
+    documents: chunk i of lane l of tile w holds the XOR of the lane's
+    loaded chunks with i added to its first word."""
+    in_a, in_b, out = shape
+    tiles = 7
+    say("stream shape %s tiles=%d" % (shape, tiles))
+    rng = np.random.default_rng(sum(shape))
+    a = rng.integers(0, 2 ** 32, size=(tiles, in_a, 64, 4), dtype=np.uint32)
+    b = rng.integers(0, 2 ** 32, size=(tiles, max(in_b, 1), 64, 4), dtype=np.uint32)[:, :in_b]
+    x = np.bitwise_xor.reduce(np.concatenate([a, b], axis=1), axis=1)          # (tiles, 64, 4)
+    want = np.repeat(x[:, None], out, axis=1)
+    want[..., 0] += np.arange(out, dtype=np.uint32)[None, :, None]
+    ta = to_dev(a.view(np.uint8).reshape(-1))
+    tb = to_dev(np.ascontiguousarray(b).view(np.uint8).reshape(-1)) if in_b else None
+    tc = torch.zeros(tiles * out * 1024, dtype=torch.uint8, device=ta.device)
+    ops.stream_shape(ta, tb, tc, in_a, in_b, out, waves_per_cu=8)
+    got = tc.cpu().numpy().view(np.uint32).reshape(tiles, out, 64, 4)
+    assert np.array_equal(got, want)
+
+
+def test_stream_copy_bytes(ops):
+    """The bandwidth reference copies every byte, ragged sizes included."""
+    say("stream copy")
+    rng = np.random.default_rng(5)
+    for n in (16, 1024, 1040, 65536 * 16 + 48):
+        src = to_dev(rng.integers(0, 256, size=n, dtype=np.uint8))
+        dst = torch.zeros_like(src)
+        ops.stream_copy(src, dst)
+        assert torch.equal(src, dst)
