@@ -37,7 +37,8 @@ namespace su3 {
 constexpr int kBwdWaves = 3;                 // wavefronts per workgroup
 constexpr int kBwdThreads = 64 * kBwdWaves;
 // Tiles per wavefront and resident wavefronts per CU for stage 1 (0: as many
-// as fit), measured at L=32 over 1, 2, 4, 8 tiles and 6, 9 or 12 wavefronts.
+// as fit), measured at L=32 over 1, 2, 3, 4, 6, 8 and 16 tiles and 3, 6, 9 or
+// 12 wavefronts.
 // More tiles per wavefront amortise the closing reduction; fewer shorten the
 // drain at the end of the grid.
 #ifndef SU3_BWD_TILES_F64
@@ -315,8 +316,8 @@ __global__ __launch_bounds__(kBlock) void bwd_chunk_sums(const double *__restric
         ws2[(int64_t)(4 * blockIdx.y + threadIdx.x) * chunks + c] = red[threadIdx.x][0];
 }
 
-// grid = 72 workgroups, one per real component of dB; ws is component-major
-// with `groups` values per component
+// grid = 72 workgroups, one per real component of dB; the input holds
+// `groups` values per component, component-major (the run sums of stage 2a)
 __global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ ws, double *__restrict__ db,
                                                      int64_t groups)
 {
