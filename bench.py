@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 FLOP_PER_SITE = 864            # paper's count: 4 x 27 x (4 mul + 4 add)
 # algorithmic bytes per site: a read once + c written once (b ignored)
 BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "f32": 576, "bf16": 288, "r12": 480,
-                  "r12c": 384, "r12f64": 960, "na": 1152, "an": 1152, "matvec": 816}
+                  "r12c": 384, "r12f64": 960, "na": 1152, "an": 1152, "matvec": 816,
+                  "soa32": 576, "na32": 576, "an32": 576, "matvec32": 408}
 BWD_BYTES_PER_SITE = {"f64": 3 * 576, "f32": 3 * 288}   # a, dC read; dA written
 # The paper's own figures for this kernel, on its hardware (context, not a
 # target): 864 flop per site, sites/s = GF/s * 1e9 / 864.
@@ -139,7 +140,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
-    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,copy,shapes,bwd")
+    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,copy,shapes,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -295,6 +296,25 @@ def main() -> int:
         ms = time_launches(lambda: ops.mat_vec(ta, tv, out=w), args.steps, args.warmup, torch)
         record("matvec", ms, BYTES_PER_SITE["matvec"], sites)
         del tv, w
+    # ---- FP32 variants of the SoA product and the other products ------------
+    if "fp32more" in forms:
+        t32 = ta.to(torch.complex64)
+        sa = ops.aos_to_soa(t32)
+        sc = torch.empty_like(sa)
+        record("soa32", time_launches(lambda: ops.mult_nn_soa(sa, tb32, out=sc), args.steps, args.warmup, torch),
+               BYTES_PER_SITE["soa32"], sites)
+        del sa, sc
+        y = torch.empty_like(t32)
+        for name, fn in (("na32", ops.mult_na), ("an32", ops.mult_an)):
+            record(name, time_launches(lambda: fn(t32, tb32, out=y), args.steps, args.warmup, torch),
+                   BYTES_PER_SITE[name], sites)
+        del y
+        tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=4)[:, 0, 0, :].copy()).to(dev)
+        tv = tv.to(torch.complex64)
+        w = ops.mat_vec(t32, tv)
+        record("matvec32", time_launches(lambda: ops.mat_vec(t32, tv, out=w), args.steps, args.warmup, torch),
+               BYTES_PER_SITE["matvec32"], sites)
+        del t32, tv, w
     for name in ("f32", "bf16", "r12", "r12c", "r12f64", "soa"):
         if name in results:
             results[name]["speedup_vs_f64"] = ms64 / results[name]["ms"]
