@@ -320,6 +320,15 @@ def main() -> int:
     for name in ("f32", "bf16", "r12", "r12c", "r12f64", "soa"):
         if name in results:
             results[name]["speedup_vs_f64"] = ms64 / results[name]["ms"]
+    # the paper counts a read and c written as its padded Site struct, 640 B
+    # (FP64) or 320 B (FP32) each, and ignores b (section Background)
+    for name, padded in (("f64", 1280), ("f32", 640)):
+        if name in results:
+            results[name]["gb_s_paper_convention"] = padded * results[name]["sites_per_s"] / 1e9
+    if "copy" in results:
+        for name, r in results.items():
+            if name not in ("copy", "shapes") and "gb_s" in r:
+                r["frac_of_measured_copy"] = r["gb_s"] / results["copy"]["gb_s"]
 
     # ---- adjoint (L = bwd-L) -----------------------------------------------
     if "bwd" in forms:
