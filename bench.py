@@ -97,7 +97,7 @@ def traffic_record():
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline_leg(a, b, sample_idx, seconds: float):
+def cpu_baseline_leg(a, b, sample_idx, seconds: float, L: int):
     """The oracle (plain single-threaded C, FP64) timed on the host on a
     bounded sample of the same workload, and its reference values on the
     sampled sites used for the error report."""
@@ -117,8 +117,8 @@ def cpu_baseline_leg(a, b, sample_idx, seconds: float):
     rate = passes * sample.shape[0] / el
     ref = O.mult_nn(a[sample_idx], b)
     rec = {"value": rate, "unit": "sites/s", "cores": 1, "kind": "oracle",
-           "sample": "first %d sites of the L=48 lattice, FP64 AoS, %d passes in %.1f s, single thread"
-                     % (sample.shape[0], passes, el),
+           "sample": "first %d sites of the L=%d lattice, FP64 AoS, %d passes in %.1f s, single thread"
+                     % (sample.shape[0], L, passes, el),
            "gb_s": rate * 1152 / 1e9, "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
     return rec, ref, O
 
@@ -348,9 +348,9 @@ def main() -> int:
     # ---- CPU baseline (oracle) and error report on sampled sites -------------
     cpu = None
     if not args.no_cpu_baseline:
-        idx = np.unique(np.concatenate([np.random.default_rng(48).choice(sites, 4096, replace=False),
+        idx = np.unique(np.concatenate([np.random.default_rng(48).choice(sites, min(4096, sites), replace=False),
                                         [0, sites - 1]]))
-        cpu, ref, O = cpu_baseline_leg(a, b, idx, args.cpu_seconds)
+        cpu, ref, O = cpu_baseline_leg(a, b, idx, args.cpu_seconds, L)
         log("oracle on host: %.3e sites/s (%s)" % (cpu["value"], cpu["sample"]))
         tidx = torch.from_numpy(idx).to(dev)
         for name, out in outputs.items():
