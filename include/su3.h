@@ -110,8 +110,10 @@ int su3_mult_nn(const void *a, const void *b, void *c, int64_t sites,
                 int precision, void *stream);
 
 /*
- * The two other link products of the MILC family the benchmark is drawn
- * from (they are also the two contractions of the adjoint):
+ * The two other link products of the MILC code the benchmark's kernel is
+ * derived from (arXiv 2103.00571, section Introduction: SU(3) matrix-matrix
+ * operations as a building block of lattice QCD); they are also the two
+ * contractions of the adjoint (su3_mult_nn_bwd):
  *   su3_mult_na: c[s][j] = a[s][j] * b[j]^H,  c(k, l) = sum_m a(k, m) conj(b(l, m))
  *   su3_mult_an: c[s][j] = a[s][j]^H * b[j],  c(k, l) = sum_m conj(a(m, k)) b(m, l)
  * Site-major layout, SU3_F64 and SU3_F32 only (other forms return
