@@ -47,7 +47,11 @@ int status_of(hipError_t e) { return e == hipSuccess ? SU3_OK : SU3_ERR_HIP; }
 // dimension (far beyond any lattice that fits in one GPU's memory).
 constexpr int64_t kMaxGridThreads = (int64_t)1 << 32;
 
-bool grid_fits(int64_t blocks, int64_t threads) { return blocks * threads < kMaxGridThreads; }
+bool grid_fits(int64_t blocks, int64_t threads)
+{
+    // blocks * threads < 2^32, without forming the product
+    return blocks >= 0 && threads > 0 && blocks <= (kMaxGridThreads - 1) / threads;
+}
 
 int check_lattice(const void *a, const void *b, const void *c, int64_t sites, int precision, Form &f)
 {
@@ -296,7 +300,9 @@ int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int i
 {
     if (!stream_shape_supported(in_a, in_b, out))
         return SU3_ERR_SIZE;
-    if (tiles < 0 || waves_per_cu < 0 || waves_per_cu > 32 || tiles > kMaxSites)
+    // the grid check first: it bounds tiles (below 2^26), so the byte counts
+    // below cannot overflow
+    if (tiles < 0 || waves_per_cu < 0 || waves_per_cu > 32 || !grid_fits(tiles, 64))
         return SU3_ERR_SIZE;
     if (tiles == 0)
         return SU3_OK;
@@ -307,8 +313,6 @@ int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int i
     const int64_t na = tiles * 1024 * in_a, nb = tiles * 1024 * in_b, nc = tiles * 1024 * out;
     if (overlap(c, nc, a, na) || (in_b > 0 && overlap(c, nc, b, nb)))
         return SU3_ERR_OVERLAP;
-    if (!grid_fits(tiles, 64))
-        return SU3_ERR_SIZE;
     return status_of(launch_stream_shape(a, b, c, tiles, in_a, in_b, out, waves_per_cu, (hipStream_t)stream));
 }
 

@@ -157,6 +157,9 @@ def test_stream_shape_validation(abi):
     assert f(A, 0, C, 4, 2, 0, 2, 0, None) == abi.SU3_ERR_SIZE           # not a kernel's shape
     assert f(A, 0, C, -1, 3, 0, 3, 0, None) == abi.SU3_ERR_SIZE
     assert f(A, 0, C, 4, 3, 0, 3, 33, None) == abi.SU3_ERR_SIZE
+    assert f(A, 0, C, 1 << 26, 3, 0, 3, 0, None) == abi.SU3_ERR_SIZE      # grid beyond 2^32 work-items
+    assert f(A, 0, C, (1 << 62) // 1024, 9, 0, 9, 0, None) == abi.SU3_ERR_SIZE   # sizes would overflow
+    assert f(A, 0, C, (1 << 63) - 1, 9, 0, 9, 0, None) == abi.SU3_ERR_SIZE      # so would the grid product
     assert f(0, 0, C, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_NULL
     assert f(A, 0, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_NULL           # b needed
     assert f(A + 8, 0, C, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_ALIGN
