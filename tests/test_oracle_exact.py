@@ -66,3 +66,32 @@ def test_adjoint_exact(O, sites, seed):
     A, B, G = _embed(a), _embed(b)[None], _embed(dc)
     assert _same(da, _unembed(G @ _T(B)))
     assert _same(db, _unembed((_T(A) @ G).sum(axis=0)))
+
+
+@settings(max_examples=30, deadline=None)
+@given(sites=SIZES, seed=SEEDS)
+def test_form_emulators_exact(O, sites, seed):
+    """The FP32, BF16 and reconstruct-12 emulators on integer entries: FP32
+    arithmetic is exact here (magnitudes far below 2^24), so the FP32 and
+    reconstruct-12 products equal the integer products bit for bit, and the
+    BF16 product equals the integer product rounded once to BF16 (by torch,
+    to nearest even)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    a, b = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3))
+    A, B = _embed(a), _embed(b)[None]
+    exact = _unembed(A @ B)
+    b32 = b.astype(np.complex64)
+    c32 = O.mult_nn_f32(a.astype(np.complex64), b32)
+    assert np.array_equal(c32.view(np.float32), exact.astype(np.complex64).view(np.float32))
+    c16 = O.mult_nn_bf16(O.round_bf16(a), b32)                              # uint16 (..., 2)
+    want16 = torch.from_numpy(exact.view(np.float64).reshape(c16.shape)).to(torch.float32).to(torch.bfloat16)
+    assert np.array_equal(c16.view(np.int16), want16.view(torch.int16).numpy())
+    r0, r1 = a[..., 0, :], a[..., 1, :]
+    row2 = np.conj(np.stack([r0[..., 1] * r1[..., 2] - r0[..., 2] * r1[..., 1],
+                             r0[..., 2] * r1[..., 0] - r0[..., 0] * r1[..., 2],
+                             r0[..., 0] * r1[..., 1] - r0[..., 1] * r1[..., 0]], -1))
+    a12 = a.copy()
+    a12[:, :, 2, :] = row2
+    c12 = O.mult_nn_r12(O.pack_r12(a), b32)
+    assert np.array_equal(c12.view(np.float32), _unembed(_embed(a12) @ B).astype(np.complex64).view(np.float32))
