@@ -141,7 +141,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
-    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,copy,shapes,bwd")
+    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,setup,copy,shapes,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -298,6 +298,32 @@ def main() -> int:
         ms = time_launches(lambda: ops.mat_vec(ta, tv, out=w), args.steps, args.warmup, torch)
         record("matvec", ms, BYTES_PER_SITE["matvec"], sites)
         del tv, w
+    # ---- setup kernels: layout transforms and storage-form conversions -------
+    # (off the product's timed path; bytes = source read + destination written)
+    if "setup" in forms:
+        t0s = time.perf_counter()
+        k = max(10, args.steps // 5)
+        sa = ops.aos_to_soa(ta)
+        back = ops.soa_to_aos(sa)
+        setup = {}
+
+        def rec_setup(name, fn, nbytes):
+            ms = time_launches(fn, k, 3, torch)
+            setup[name] = {"ms": ms, "gb_s": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes}
+            log("setup %-12s %8.4f ms  %7.1f GB/s" % (name, ms, nbytes / (ms * 1e-3) / 1e9))
+
+        rec_setup("aos_to_soa", lambda: ops.aos_to_soa(ta), 1152 * sites)
+        rec_setup("soa_to_aos", lambda: ops.soa_to_aos(sa), 1152 * sites)
+        del sa, back
+        for name, code, packed in (("f32", ops.SU3_F32, 288), ("bf16", ops.SU3_BF16, 144),
+                                   ("r12", ops.SU3_R12_F32, 192), ("r12f64", ops.SU3_R12_F64, 384)):
+            x = ops.pack(ta, code)
+            rec_setup("pack_" + name, lambda: ops.pack(ta, code), (576 + packed) * sites)
+            rec_setup("unpack_" + name, lambda: ops.unpack(x), (packed + 576) * sites)
+            del x
+        results["setup"] = setup
+        log("setup leg %.1f s" % (time.perf_counter() - t0s))
+
     # ---- FP32 variants of the SoA product and the other products ------------
     if "fp32more" in forms:
         t32 = ta.to(torch.complex64)
@@ -327,7 +353,7 @@ def main() -> int:
             results[name]["gb_s_paper_convention"] = padded * results[name]["sites_per_s"] / 1e9
     if "copy" in results:
         for name, r in results.items():
-            if name not in ("copy", "shapes") and "gb_s" in r:
+            if name not in ("copy", "shapes", "setup") and "gb_s" in r:
                 r["frac_of_measured_copy"] = r["gb_s"] / results["copy"]["gb_s"]
 
     # ---- adjoint (L = bwd-L) -----------------------------------------------
