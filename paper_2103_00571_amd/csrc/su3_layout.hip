@@ -3,6 +3,12 @@
 // and the plain streaming copy used as the bandwidth reference.
 #include "su3_internal.hpp"
 
+// Resident wavefronts per CU for the reconstruct-12 unpack (9 KiB of stores
+// and 3 or 6 KiB of loads per wavefront).
+#ifndef SU3_WAVES_UNPACK_R12
+#define SU3_WAVES_UNPACK_R12 6
+#endif
+
 namespace su3 {
 
 // ------------------------------------------------------------ AoS <-> SoA
@@ -114,31 +120,70 @@ __global__ __launch_bounds__(kBlock) void unpack_bf16(const uint32_t *__restrict
 // in the order (r0_p r1_q) - (r0_q r1_p) with each complex product formed as
 // (re*re - im*im, re*im + im*re). The result is then a fixed function of the
 // stored rows, independent of compiler contraction choices.
+// One wavefront per tile of 64 links, the streaming pattern of the product
+// kernels: the tile's rows 0-1 (3 chunks per link in FP32, 6 in FP64) and its
+// full FP64 links (9 chunks each) move in whole-wavefront 1 KiB runs, and a
+// private LDS slice turns them into one link per lane. Row 2 is rebuilt in
+// FP64 with contraction off, in the oracle's operation order, so the result
+// is bit-exact.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void unpack_r12(const V *__restrict__ src, d2 *__restrict__ dst, int64_t links)
+__global__ __launch_bounds__(64) void unpack_r12(const u4 *__restrict__ src, u4 *__restrict__ dst, int64_t links)
 {
 #pragma clang fp contract(off)
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
-        double r[12];
+    constexpr int kIn = sizeof(V) == 8 ? 3 : 6;   // input chunks per link
+    __shared__ u4 stage[64 * 9];
+    const int lane = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t nin = links * kIn, nout = links * 9;
+    const bool whole = (t + 1) * 64 <= links;
+    u4 v[kIn];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const V v = src[6 * t + q];
-            r[2 * q] = (double)v.x;
-            r[2 * q + 1] = (double)v.y;
-            d2 o = {r[2 * q], r[2 * q + 1]};
-            dst[9 * t + q] = o;
-        }
-        const double *r0 = r, *r1 = r + 6;
+    for (int i = 0; i < kIn; ++i) {
+        const int64_t g = t * 64 * kIn + 64 * i + lane;
+        v[i] = ld_stream(src + (g < nin ? g : nin - 1));   // in bounds; unused past the end
+    }
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int p = (l + 1) % 3, q = (l + 2) % 3;
-            const double pr = r0[2 * p] * r1[2 * q] - r0[2 * p + 1] * r1[2 * q + 1];
-            const double pi = r0[2 * p] * r1[2 * q + 1] + r0[2 * p + 1] * r1[2 * q];
-            const double qr = r0[2 * q] * r1[2 * p] - r0[2 * q + 1] * r1[2 * p + 1];
-            const double qi = r0[2 * q] * r1[2 * p + 1] + r0[2 * q + 1] * r1[2 * p];
-            d2 o = {pr - qr, -(pi - qi)};
-            dst[9 * t + 6 + l] = o;
-        }
+    for (int i = 0; i < kIn; ++i)
+        stage[64 * i + lane] = v[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double r[12];
+    const V *in = reinterpret_cast<const V *>(stage) + 6 * lane;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const V w = in[q];
+        r[2 * q] = (double)w.x;
+        r[2 * q + 1] = (double)w.y;
+    }
+    d2 o[9];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        o[q] = d2{r[2 * q], r[2 * q + 1]};
+    const double *r0 = r, *r1 = r + 6;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int p = (l + 1) % 3, q = (l + 2) % 3;
+        const double pr = r0[2 * p] * r1[2 * q] - r0[2 * p + 1] * r1[2 * q + 1];
+        const double pi = r0[2 * p] * r1[2 * q + 1] + r0[2 * p + 1] * r1[2 * q];
+        const double qr = r0[2 * q] * r1[2 * p] - r0[2 * q + 1] * r1[2 * p + 1];
+        const double qi = r0[2 * q] * r1[2 * p + 1] + r0[2 * q + 1] * r1[2 * p];
+        o[6 + l] = d2{pr - qr, -(pi - qi)};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        stage[9 * lane + q] = __builtin_bit_cast(u4, o[q]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int64_t g = t * 64 * 9 + 64 * i + lane;
+        if (whole || g < nout)
+            st_stream(dst + g, stage[64 * i + lane]);
     }
 }
 
@@ -287,12 +332,18 @@ hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precisio
         return launch_k(unpack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const uint32_t *)src,
                         (d2 *)dst, elems);
     case 3:
-    case 4:
-        return launch_k(unpack_r12<f2>, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const f2 *)src, (d2 *)dst,
-                        links);
-    case 5:
-        return launch_k(unpack_r12<d2>, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst,
-                        links);
+    case 4: {
+        static std::atomic<int> pad[kMaxDevices];
+        const size_t p = occupancy_pad(reinterpret_cast<const void *>(unpack_r12<f2>), SU3_WAVES_UNPACK_R12, 64, pad);
+        return launch_k(unpack_r12<f2>, dim3((unsigned)((links + 63) / 64)), dim3(64), s, p, (const u4 *)src,
+                        (u4 *)dst, links);
+    }
+    case 5: {
+        static std::atomic<int> pad[kMaxDevices];
+        const size_t p = occupancy_pad(reinterpret_cast<const void *>(unpack_r12<d2>), SU3_WAVES_UNPACK_R12, 64, pad);
+        return launch_k(unpack_r12<d2>, dim3((unsigned)((links + 63) / 64)), dim3(64), s, p, (const u4 *)src,
+                        (u4 *)dst, links);
+    }
     default:
         return launch_stream_copy(src, dst, elems * 16, s);
     }
