@@ -11,6 +11,14 @@
 
 namespace su3 {
 
+// The setup kernels (pack, unpack, transposes) loop over their items with a
+// grid stride. Each launch picks a workgroup size and a grid cap measured at
+// L=48: kOnePass covers any lattice that fits in memory in one pass, which
+// streams faster for the elementwise FP32 and BF16 conversions; the
+// link-wise packs and the BF16 unpack stream faster on 65,536 looping
+// workgroups.
+constexpr int64_t kOnePass = (int64_t)1 << 24, kLooping = 65536;
+
 // ------------------------------------------------------------ AoS <-> SoA
 // One workgroup moves a tile of 64 sites at a time through LDS: the site-
 // major side is read or written as one contiguous run of 64*36 elements, the
@@ -52,9 +60,10 @@ __global__ __launch_bounds__(kBlock) void transpose_aos_soa(const V *__restrict_
 
 // ------------------------------------------------------------ pack
 // FP64 complex -> FP32 complex, round to nearest even (v_cvt_f32_f64).
-__global__ __launch_bounds__(kBlock) void pack_f32(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t n)
+template <int B>
+__global__ __launch_bounds__(B) void pack_f32(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t n)
 {
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < n; e += (int64_t)gridDim.x * B) {
         const d2 v = src[e];
         f2 o = {(float)v.x, (float)v.y};
         dst[e] = o;
@@ -62,19 +71,21 @@ __global__ __launch_bounds__(kBlock) void pack_f32(const d2 *__restrict__ src, f
 }
 
 // FP64 complex -> BF16 (re, im), through FP32, each step to nearest even.
-__global__ __launch_bounds__(kBlock) void pack_bf16(const d2 *__restrict__ src, uint32_t *__restrict__ dst,
+template <int B>
+__global__ __launch_bounds__(B) void pack_bf16(const d2 *__restrict__ src, uint32_t *__restrict__ dst,
                                                     int64_t n)
 {
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < n; e += (int64_t)gridDim.x * B) {
         const d2 v = src[e];
         dst[e] = pack_bf16x2((float)v.x, (float)v.y);
     }
 }
 
 // FP64 links -> rows 0 and 1 in FP32 (reconstruct-12 storage); thread per link.
-__global__ __launch_bounds__(kBlock) void pack_r12(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t links)
+template <int B>
+__global__ __launch_bounds__(B) void pack_r12(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t links)
 {
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
+    for (int64_t t = (int64_t)blockIdx.x * B + threadIdx.x; t < links; t += (int64_t)gridDim.x * B) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const d2 v = src[9 * t + q];
@@ -85,10 +96,11 @@ __global__ __launch_bounds__(kBlock) void pack_r12(const d2 *__restrict__ src, f
 }
 
 // FP64 links -> rows 0 and 1 kept in FP64 (reconstruct-12 in FP64).
-__global__ __launch_bounds__(kBlock) void pack_r12_f64(const d2 *__restrict__ src, d2 *__restrict__ dst,
+template <int B>
+__global__ __launch_bounds__(B) void pack_r12_f64(const d2 *__restrict__ src, d2 *__restrict__ dst,
                                                        int64_t links)
 {
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < links; t += (int64_t)gridDim.x * kBlock) {
+    for (int64_t t = (int64_t)blockIdx.x * B + threadIdx.x; t < links; t += (int64_t)gridDim.x * B) {
 #pragma unroll
         for (int q = 0; q < 6; ++q)
             dst[6 * t + q] = src[9 * t + q];
@@ -96,19 +108,21 @@ __global__ __launch_bounds__(kBlock) void pack_r12_f64(const d2 *__restrict__ sr
 }
 
 // ------------------------------------------------------------ unpack
-__global__ __launch_bounds__(kBlock) void unpack_f32(const f2 *__restrict__ src, d2 *__restrict__ dst, int64_t n)
+template <int B>
+__global__ __launch_bounds__(B) void unpack_f32(const f2 *__restrict__ src, d2 *__restrict__ dst, int64_t n)
 {
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < n; e += (int64_t)gridDim.x * B) {
         const f2 v = src[e];
         d2 o = {(double)v.x, (double)v.y};
         dst[e] = o;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void unpack_bf16(const uint32_t *__restrict__ src, d2 *__restrict__ dst,
+template <int B>
+__global__ __launch_bounds__(B) void unpack_bf16(const uint32_t *__restrict__ src, d2 *__restrict__ dst,
                                                       int64_t n)
 {
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < n; e += (int64_t)gridDim.x * B) {
         const uint32_t w = src[e];
         d2 o = {(double)bf16_lo(w), (double)bf16_hi(w)};
         dst[e] = o;
@@ -234,11 +248,11 @@ __global__ __launch_bounds__(64) void stream_shape(const u4 *__restrict__ a, con
 }
 
 // ------------------------------------------------------------ launchers
-static unsigned grid_for(int64_t items, int64_t per_block)
+static unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = kOnePass)
 {
     int64_t g = (items + per_block - 1) / per_block;
-    if (g > 65536)
-        g = 65536;
+    if (g > cap)
+        g = cap;
     if (g < 1)
         g = 1;
     return (unsigned)g;
@@ -306,15 +320,17 @@ hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision,
     const int64_t elems = sites * 36, links = sites * 4;
     switch (precision) {
     case 1:
-        return launch_k(pack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (f2 *)dst, elems);
+        return launch_k(pack_f32<64>, dim3(grid_for(elems, 64, kOnePass)), dim3(64), s, 0, (const d2 *)src,
+                        (f2 *)dst, elems);
     case 2:
-        return launch_k(pack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const d2 *)src,
+        return launch_k(pack_bf16<128>, dim3(grid_for(elems, 128, kOnePass)), dim3(128), s, 0, (const d2 *)src,
                         (uint32_t *)dst, elems);
     case 3:
     case 4:
-        return launch_k(pack_r12, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (f2 *)dst, links);
+        return launch_k(pack_r12<256>, dim3(grid_for(links, 256, kLooping)), dim3(256), s, 0, (const d2 *)src,
+                        (f2 *)dst, links);
     case 5:
-        return launch_k(pack_r12_f64, dim3(grid_for(links, kBlock)), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst,
+        return launch_k(pack_r12_f64<256>, dim3(grid_for(links, 256, kLooping)), dim3(256), s, 0, (const d2 *)src, (d2 *)dst,
                         links);
     default:
         return launch_stream_copy(src, dst, elems * 16, s);
@@ -326,10 +342,10 @@ hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precisio
     const int64_t elems = sites * 36, links = sites * 4;
     switch (precision) {
     case 1:
-        return launch_k(unpack_f32, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const f2 *)src, (d2 *)dst,
+        return launch_k(unpack_f32<64>, dim3(grid_for(elems, 64, kOnePass)), dim3(64), s, 0, (const f2 *)src, (d2 *)dst,
                         elems);
     case 2:
-        return launch_k(unpack_bf16, dim3(grid_for(elems, kBlock)), dim3(kBlock), s, 0, (const uint32_t *)src,
+        return launch_k(unpack_bf16<256>, dim3(grid_for(elems, 256, kLooping)), dim3(256), s, 0, (const uint32_t *)src,
                         (d2 *)dst, elems);
     case 3:
     case 4: {
