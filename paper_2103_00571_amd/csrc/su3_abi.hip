@@ -221,8 +221,8 @@ static int convert(const void *src, void *dst, int64_t sites, int precision, boo
         return SU3_ERR_OVERLAP;
     if (precision == SU3_F64 && !grid_fits(sites * 36, 1))
         return SU3_ERR_SIZE;
-    // the reconstruct-12 unpack covers the links once, 64 per workgroup
-    if (!pack && (precision == SU3_R12_F32 || precision == SU3_R12C_F32 || precision == SU3_R12_F64) &&
+    // the reconstruct-12 pack and unpack cover the links once, 64 per workgroup
+    if ((precision == SU3_R12_F32 || precision == SU3_R12C_F32 || precision == SU3_R12_F64) &&
         !grid_fits((sites * 4 + 63) / 64, 64))
         return SU3_ERR_SIZE;
     hipStream_t s = (hipStream_t)stream;

@@ -3,10 +3,16 @@
 // and the plain streaming copy used as the bandwidth reference.
 #include "su3_internal.hpp"
 
+#include <type_traits>
+
 // Resident wavefronts per CU for the reconstruct-12 unpack (9 KiB of stores
 // and 3 or 6 KiB of loads per wavefront).
 #ifndef SU3_WAVES_UNPACK_R12
 #define SU3_WAVES_UNPACK_R12 6
+#endif
+// ... and for the reconstruct-12 pack (9 KiB of loads per wavefront).
+#ifndef SU3_WAVES_PACK_R12
+#define SU3_WAVES_PACK_R12 6
 #endif
 
 namespace su3 {
@@ -81,29 +87,53 @@ __global__ __launch_bounds__(B) void pack_bf16(const d2 *__restrict__ src, uint3
     }
 }
 
-// FP64 links -> rows 0 and 1 in FP32 (reconstruct-12 storage); thread per link.
-template <int B>
-__global__ __launch_bounds__(B) void pack_r12(const d2 *__restrict__ src, f2 *__restrict__ dst, int64_t links)
+// FP64 links -> rows 0 and 1 in FP32 (V = f2, round to nearest even) or FP64
+// (V = d2), the reconstruct-12 storage. One wavefront per tile of 64 links:
+// whole-wavefront 1 KiB runs of the tile's links (9 chunks each) in, the
+// rows 0-1 of each (3 or 6 chunks) out, through a private LDS slice.
+template <typename V>
+__global__ __launch_bounds__(64) void pack_r12(const u4 *__restrict__ src, u4 *__restrict__ dst, int64_t links)
 {
-    for (int64_t t = (int64_t)blockIdx.x * B + threadIdx.x; t < links; t += (int64_t)gridDim.x * B) {
+    constexpr int kOut = sizeof(V) == 8 ? 3 : 6;   // output chunks per link
+    __shared__ u4 stage[64 * 9];
+    const int lane = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t nin = links * 9, nout = links * kOut;
+    const bool whole = (t + 1) * 64 <= links;
+    u4 v[9];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const d2 v = src[9 * t + q];
-            f2 o = {(float)v.x, (float)v.y};
-            dst[6 * t + q] = o;
-        }
+    for (int i = 0; i < 9; ++i) {
+        const int64_t g = t * 64 * 9 + 64 * i + lane;
+        v[i] = ld_stream(src + (g < nin ? g : nin - 1));   // in bounds; unused past the end
     }
-}
-
-// FP64 links -> rows 0 and 1 kept in FP64 (reconstruct-12 in FP64).
-template <int B>
-__global__ __launch_bounds__(B) void pack_r12_f64(const d2 *__restrict__ src, d2 *__restrict__ dst,
-                                                       int64_t links)
-{
-    for (int64_t t = (int64_t)blockIdx.x * B + threadIdx.x; t < links; t += (int64_t)gridDim.x * B) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
-            dst[6 * t + q] = src[9 * t + q];
+    for (int i = 0; i < 9; ++i)
+        stage[64 * i + lane] = v[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    typedef typename std::conditional<sizeof(V) == 8, float, double>::type E;   // element of V
+    V o[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const d2 w = __builtin_bit_cast(d2, stage[9 * lane + q]);
+        o[q] = V{(E)w.x, (E)w.y};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    V *out = reinterpret_cast<V *>(stage) + 6 * lane;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        out[q] = o[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int i = 0; i < kOut; ++i) {
+        const int64_t g = t * 64 * kOut + 64 * i + lane;
+        if (whole || g < nout)
+            st_stream(dst + g, stage[64 * i + lane]);
     }
 }
 
@@ -312,6 +342,15 @@ hipError_t launch_stream_shape(const void *a, const void *b, void *c, int64_t ti
     return hipErrorInvalidValue;
 }
 
+template <typename V>
+static hipError_t launch_pack_r12(const void *src, void *dst, int64_t links, hipStream_t s)
+{
+    static std::atomic<int> pad[kMaxDevices];
+    const size_t p = occupancy_pad(reinterpret_cast<const void *>(pack_r12<V>), SU3_WAVES_PACK_R12, 64, pad);
+    return launch_k(pack_r12<V>, dim3((unsigned)((links + 63) / 64)), dim3(64), s, p, (const u4 *)src, (u4 *)dst,
+                    links);
+}
+
 // precision codes as in su3.h: 0 F64, 1 F32, 2 BF16, 3 R12_F32 (rows 0-1 FP32
 // in, full FP32 out), 4 R12C_F32 (rows 0-1 FP32 in and out), 5 R12_F64 (rows
 // 0-1 FP64 in, full FP64 out). Codes 3 and 4 share the storage of a.
@@ -327,11 +366,9 @@ hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision,
                         (uint32_t *)dst, elems);
     case 3:
     case 4:
-        return launch_k(pack_r12<256>, dim3(grid_for(links, 256, kLooping)), dim3(256), s, 0, (const d2 *)src,
-                        (f2 *)dst, links);
+        return launch_pack_r12<f2>(src, dst, links, s);
     case 5:
-        return launch_k(pack_r12_f64<256>, dim3(grid_for(links, 256, kLooping)), dim3(256), s, 0, (const d2 *)src, (d2 *)dst,
-                        links);
+        return launch_pack_r12<d2>(src, dst, links, s);
     default:
         return launch_stream_copy(src, dst, elems * 16, s);
     }
