@@ -17,13 +17,13 @@
 
 namespace su3 {
 
-// The setup kernels (pack, unpack, transposes) loop over their items with a
-// grid stride. Each launch picks a workgroup size and a grid cap measured at
-// L=48: kOnePass covers any lattice that fits in memory in one pass, which
-// streams faster for the elementwise FP32 and BF16 conversions; the
-// link-wise packs and the BF16 unpack stream faster on 65,536 looping
-// workgroups.
-constexpr int64_t kOnePass = (int64_t)1 << 24, kLooping = 65536;
+// The elementwise setup kernels (FP32 and BF16 pack and unpack, transposes)
+// loop over their items with a grid stride, on a grid of up to kOnePass
+// workgroups: one pass for any lattice that fits in memory, which streams
+// faster than fewer workgroups looping.
+constexpr int64_t kOnePass = (int64_t)1 << 24;
+
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------ AoS <-> SoA
 // One workgroup moves a tile of 64 sites at a time through LDS: the site-
@@ -148,14 +148,17 @@ __global__ __launch_bounds__(B) void unpack_f32(const f2 *__restrict__ src, d2 *
     }
 }
 
+// BF16 -> FP64, exact; two complex numbers per thread (one 8-byte load, two
+// 16-byte stores). n2 = number of pairs (36 complex per site, so no odd one).
 template <int B>
-__global__ __launch_bounds__(B) void unpack_bf16(const uint32_t *__restrict__ src, d2 *__restrict__ dst,
-                                                      int64_t n)
+__global__ __launch_bounds__(B) void unpack_bf16(const u2 *__restrict__ src, d2 *__restrict__ dst, int64_t n2)
 {
-    for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < n; e += (int64_t)gridDim.x * B) {
-        const uint32_t w = src[e];
-        d2 o = {(double)bf16_lo(w), (double)bf16_hi(w)};
-        dst[e] = o;
+    for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < n2; e += (int64_t)gridDim.x * B) {
+        const u2 w = src[e];
+        const d2 o0 = {(double)bf16_lo(w.x), (double)bf16_hi(w.x)};
+        const d2 o1 = {(double)bf16_lo(w.y), (double)bf16_hi(w.y)};
+        dst[2 * e] = o0;
+        dst[2 * e + 1] = o1;
     }
 }
 
@@ -382,8 +385,8 @@ hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precisio
         return launch_k(unpack_f32<64>, dim3(grid_for(elems, 64, kOnePass)), dim3(64), s, 0, (const f2 *)src, (d2 *)dst,
                         elems);
     case 2:
-        return launch_k(unpack_bf16<256>, dim3(grid_for(elems, 256, kLooping)), dim3(256), s, 0, (const uint32_t *)src,
-                        (d2 *)dst, elems);
+        return launch_k(unpack_bf16<256>, dim3(grid_for(elems / 2, 256, kOnePass)), dim3(256), s, 0, (const u2 *)src,
+                        (d2 *)dst, elems / 2);
     case 3:
     case 4: {
         static std::atomic<int> pad[kMaxDevices];
