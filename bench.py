@@ -223,30 +223,33 @@ def main() -> int:
     # shape's streaming ceiling on this GPU.
     if "shapes" in forms:
         bsites = args.bwd_L ** 4
-        shapes = [((3, 0, 3), 12 * sites // 64, "f64, f32, bf16, r12c, na"),
-                  ((1, 0, 1), 36 * sites // 64, "copy"),
-                  ((3, 3, 3), 12 * bsites // 64, "bwd_f64, bwd_f32"),
-                  ((6, 0, 9), 2 * sites // 64, "r12"),
-                  ((9, 0, 9), 4 * sites // 64, "an")]
+        # (shape, tiles, tile order of the kernels beside it, kernels)
+        shapes = [((3, 0, 3), 12 * sites // 64, 1, "f64, f32, bf16, r12c, na"),
+                  ((1, 0, 1), 36 * sites // 64, 0, "copy"),
+                  ((3, 3, 3), 12 * bsites // 64, 0, "bwd_f64, bwd_f32"),
+                  ((6, 0, 9), 2 * sites // 64, 1, "r12, r12f64"),
+                  ((9, 0, 9), 4 * sites // 64, 1, "an")]
         abytes = ta.view(torch.uint8).reshape(-1)
         bbytes = c64.view(torch.uint8).reshape(-1)
-        cbytes = torch.empty(max(t * 1024 * sh[2] for sh, t, _ in shapes), dtype=torch.uint8, device=dev)
+        cbytes = torch.empty(max(t * 1024 * sh[2] for sh, t, _, _ in shapes), dtype=torch.uint8, device=dev)
         res = {}
-        for (ia, ib, io), tiles, beside in shapes:
+        for (ia, ib, io), tiles, order, beside in shapes:
             if tiles * 1024 * max(ia, ib) > abytes.numel():
                 continue
             A, C = abytes[: tiles * 1024 * ia], cbytes[: tiles * 1024 * io]
             B = bbytes[: tiles * 1024 * ib] if ib else None
             nbytes = (ia + ib + io) * tiles * 1024
             best = None
-            for cap in (0, 32, 24, 16, 12, 11, 10, 9, 8, 6, 4):
-                ms = time_launches(lambda: ops.stream_shape(A, B, C, ia, ib, io, cap), 20, 3, torch)
+            for cap in (0, 32, 24, 16, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4):
+                ms = time_launches(lambda: ops.stream_shape(A, B, C, ia, ib, io, cap, order), 20, 3, torch)
                 gbs = nbytes / (ms * 1e-3) / 1e9
                 if best is None or gbs > best[0]:
                     best = (gbs, cap, ms)
             key = "%d+%d in, %d out" % (ia, ib, io)
-            res[key] = {"gb_s": best[0], "waves_per_cu": best[1], "ms": best[2], "bytes": nbytes, "kernels": beside}
-            log("shape %-14s ceiling %7.1f GB/s (cap %d)  beside %s" % (key, best[0], best[1], beside))
+            res[key] = {"gb_s": best[0], "waves_per_cu": best[1], "ms": best[2], "bytes": nbytes,
+                        "tile_order": "xcd" if order else "index", "kernels": beside}
+            log("shape %-14s ceiling %7.1f GB/s (cap %d, %s order)  beside %s"
+                % (key, best[0], best[1], "xcd" if order else "index", beside))
         results["shapes"] = res
         del cbytes
 

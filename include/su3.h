@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define SU3_ABI_VERSION 3
+#define SU3_ABI_VERSION 4
 
 /* storage form codes */
 enum su3_precision {
@@ -213,7 +213,14 @@ int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
  * w*1024*in_a .. (w+1)*1024*in_a - 1, as in_a whole-wavefront 1 KiB runs),
  * in_b chunks per lane from b likewise, and writes out chunks per lane to c
  * (bytes w*1024*out ..), with one 64-thread workgroup per tile and at most
- * waves_per_cu resident wavefronts per CU (0: no cap, at most 32). The
+ * waves_per_cu resident wavefronts per CU (0: no cap, at most 32).
+ * tile_order picks which workgroup takes which tile: 0, workgroup i takes
+ * tile i (the order of su3_stream_copy, su3_mult_nn_soa and the adjoint);
+ * 1, XCD-contiguous, the order of the site-major products, the matrix-vector
+ * product and the reconstruct-12 pack and unpack. MI355X deals workgroups
+ * round-robin to its 8 XCDs, and order 1 gives XCD x (the workgroups i with
+ * i mod 8 = x) one contiguous run of tiles: with q = tiles / 8 and
+ * r = tiles mod 8, its k-th workgroup takes tile x*q + min(x, r) + k. The
  * values written are the XOR of the lane's loaded chunks with the chunk
  * number added to the first word. The shapes are those of the kernels:
  * (in_a, in_b, out) = (1, 0, 1) copy; (3, 0, 3) the FP64/FP32/BF16 forward;
@@ -221,10 +228,11 @@ int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
  * (9, 0, 9) a^H b. Sizes: a holds tiles*1024*in_a bytes, b tiles*1024*in_b
  * (b may be NULL when in_b is 0), c tiles*1024*out; 16-byte aligned; c must
  * not overlap a or b. Errors: SU3_ERR_SIZE for another shape, a negative
- * count or a cap above 32; otherwise as su3_stream_copy.
+ * count, a cap above 32 or a tile_order other than 0 and 1; otherwise as
+ * su3_stream_copy.
  */
 int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
-                     int waves_per_cu, void *stream);
+                     int waves_per_cu, int tile_order, void *stream);
 
 /*
  * Launch shape the library uses for su3_mult_nn on the current device:

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsu3.so")
 
 # su3.h constants
-ABI_VERSION = 3
+ABI_VERSION = 4
 SU3_F64, SU3_F32, SU3_BF16, SU3_R12_F32, SU3_R12C_F32, SU3_R12_F64 = 0, 1, 2, 3, 4, 5
 SU3_OK = 0
 SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION = -1, -2, -3, -4
@@ -38,7 +38,7 @@ SIGNATURES = {
     "su3_mult_nn_bwd_workspace_bytes": ([_I64, _I], _SZ),
     "su3_mult_nn_bwd": ([_P, _P, _P, _P, _P, _I64, _I, _P, _SZ, _P], _I),
     "su3_stream_copy": ([_P, _P, _I64, _P], _I),
-    "su3_stream_shape": ([_P, _P, _P, _I64, _I, _I, _I, _I, _P], _I),
+    "su3_stream_shape": ([_P, _P, _P, _I64, _I, _I, _I, _I, _I, _P], _I),
     "su3_launch_shape": ([_I64, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)], _I),
 }
 
@@ -137,8 +137,8 @@ def su3_stream_copy(src: int, dst: int, nbytes: int, stream: int) -> int:
 
 
 def su3_stream_shape(a: int, b: int, c: int, tiles: int, in_a: int, in_b: int, out: int, waves_per_cu: int,
-                     stream: int) -> int:
-    return lib.su3_stream_shape(a, b, c, tiles, in_a, in_b, out, waves_per_cu, stream)
+                     tile_order: int, stream: int) -> int:
+    return lib.su3_stream_shape(a, b, c, tiles, in_a, in_b, out, waves_per_cu, tile_order, stream)
 
 
 def su3_launch_shape(sites: int, precision: int) -> tuple[int, int]:

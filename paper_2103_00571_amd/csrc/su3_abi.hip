@@ -300,13 +300,14 @@ int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream)
 }
 
 int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
-                     int waves_per_cu, void *stream)
+                     int waves_per_cu, int tile_order, void *stream)
 {
     if (!stream_shape_supported(in_a, in_b, out))
         return SU3_ERR_SIZE;
     // the grid check first: it bounds tiles (below 2^26), so the byte counts
     // below cannot overflow
-    if (tiles < 0 || waves_per_cu < 0 || waves_per_cu > 32 || !grid_fits(tiles, 64))
+    if (tiles < 0 || waves_per_cu < 0 || waves_per_cu > 32 || (tile_order != 0 && tile_order != 1) ||
+        !grid_fits(tiles, 64))
         return SU3_ERR_SIZE;
     if (tiles == 0)
         return SU3_OK;
@@ -317,7 +318,8 @@ int su3_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int i
     const int64_t na = tiles * 1024 * in_a, nb = tiles * 1024 * in_b, nc = tiles * 1024 * out;
     if (overlap(c, nc, a, na) || (in_b > 0 && overlap(c, nc, b, nb)))
         return SU3_ERR_OVERLAP;
-    return status_of(launch_stream_shape(a, b, c, tiles, in_a, in_b, out, waves_per_cu, (hipStream_t)stream));
+    return status_of(
+        launch_stream_shape(a, b, c, tiles, in_a, in_b, out, waves_per_cu, tile_order, (hipStream_t)stream));
 }
 
 } // extern "C"

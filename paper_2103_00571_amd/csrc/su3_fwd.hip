@@ -26,14 +26,14 @@
 
 // Resident wavefronts per CU, per kernel. Fewer resident wavefronts mean
 // fewer bytes in flight; on MI355X the streaming rate of these kernels peaks
-// with about 33-36 KiB of loads in flight per CU (11-12 wavefronts of 3 KiB)
-// and falls steeply below about 9. Values from a sweep at L=48; 0 leaves
-// occupancy to the hardware.
+// with about 36-39 KiB of loads in flight per CU (12-13 wavefronts of 3 KiB,
+// in the XCD-contiguous tile order) and falls steeply below about 9. Values
+// from a sweep at L=48; 0 leaves occupancy to the hardware.
 #ifndef SU3_WAVES_F64
-#define SU3_WAVES_F64 11
+#define SU3_WAVES_F64 12
 #endif
 #ifndef SU3_WAVES_F32
-#define SU3_WAVES_F32 12
+#define SU3_WAVES_F32 13
 #endif
 #ifndef SU3_WAVES_BF16
 #define SU3_WAVES_BF16 14
@@ -43,13 +43,13 @@
 #endif
 // (R12C: 3 KiB of loads per wavefront, like FP64; R12F64: 6 KiB; AN: 9 KiB.)
 #ifndef SU3_WAVES_R12C
-#define SU3_WAVES_R12C 12
+#define SU3_WAVES_R12C 13
 #endif
 #ifndef SU3_WAVES_R12F64
 #define SU3_WAVES_R12F64 6
 #endif
 #ifndef SU3_WAVES_AN
-#define SU3_WAVES_AN 4
+#define SU3_WAVES_AN 6
 #endif
 #ifndef SU3_WAVES_SOA_F64
 #define SU3_WAVES_SOA_F64 8
@@ -383,10 +383,12 @@ __device__ __forceinline__ void wave_sync()
 // consecutive units and exits: its global loads and stores are whole 1 KiB
 // runs (lane l moves chunk i*64 + l of the tile), and a private LDS slice
 // transposes between that order and one unit per lane (lane l reads chunks
-// l*kIn .. l*kIn+kIn-1). The grid covers the lattice once, so the hardware
-// dispatcher issues tiles in address order; on MI355X this streams faster
-// than a persistent grid-stride loop (which lets workgroups drift apart in
-// memory). The four b links are staged once per workgroup in LDS and each
+// l*kIn .. l*kIn+kIn-1). The grid covers the lattice once and each XCD
+// takes one contiguous eighth of the tiles (xcd_tile), which it streams in
+// address order; on MI355X this is faster than a persistent grid-stride
+// loop (which lets workgroups drift apart in memory), than tile =
+// workgroup index, and than several tiles per wavefront with the next
+// tile's loads in flight during the current one's compute. The four b links are staged once per workgroup in LDS and each
 // lane reads the coefficients of its own unit position from there.
 // kConjB: stage b[j]^H instead of b[j] (the a b^H product; the kernel is
 // otherwise the same).
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 
     const int lane = threadIdx.x & 63;
     u4 *my = stage[threadIdx.x >> 6];
-    const int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     const bool live = t * 64 < units;            // wave-uniform
     const bool whole = (t + 1) * 64 <= units;    // wave-uniform (no ragged end)
     const int64_t nin = units * F::kIn, nout = units * F::kOut;

@@ -52,6 +52,32 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2));
 }
 
+// XCD-contiguous tile order of a one-pass grid of nb workgroups. The
+// dispatcher deals workgroups round-robin to MI355X's 8 XCDs (workgroup i to
+// XCD i mod 8); here the k-th workgroup of XCD x takes tile
+// x*q + min(x, r) + k (q = nb / 8, r = nb mod 8), so each XCD streams one
+// contiguous eighth of the buffers in address order instead of every eighth
+// tile. A bijection on [0, nb) for any nb: XCD x owns q tiles, plus one if
+// x < r.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t nb)
+{
+    const int64_t q = nb / kXcds, r = nb % kXcds, x = bid % kXcds;
+    return x * q + (x < r ? x : r) + bid / kXcds;
+}
+
+// The tile of this workgroup in the site-major products, the matrix-vector
+// product and the reconstruct-12 pack and unpack: XCD-contiguous (at L = 48
+// it streams 3-5% faster than tile = workgroup index at the best cap of
+// each). SU3_XCD_ORDER 0 restores tile = workgroup index.
+#ifndef SU3_XCD_ORDER
+#define SU3_XCD_ORDER 1
+#endif
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nb)
+{
+    return SU3_XCD_ORDER ? xcd_order(bid, nb) : bid;
+}
+
 // Threads per workgroup of the streaming kernels: four wave64s.
 constexpr int kBlock = 256;
 
@@ -109,7 +135,7 @@ hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStre
 // shape it does not implement.
 bool stream_shape_supported(int in_a, int in_b, int out);
 hipError_t launch_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
-                               int waves_per_cu, hipStream_t s);
+                               int waves_per_cu, int tile_order, hipStream_t s);
 // Adjoint: stage 1 writes per-workgroup partial sums of db into ws (72 x
 // bwd_groups doubles, in 32-byte quads of components), stage 2 reduces them in a fixed order
 // through run sums stored after them; bwd_workspace_doubles is the total.

@@ -8,7 +8,7 @@
 // Resident wavefronts per CU for the reconstruct-12 unpack (9 KiB of stores
 // and 3 or 6 KiB of loads per wavefront).
 #ifndef SU3_WAVES_UNPACK_R12
-#define SU3_WAVES_UNPACK_R12 6
+#define SU3_WAVES_UNPACK_R12 7
 #endif
 // ... and for the reconstruct-12 pack (9 KiB of loads per wavefront).
 #ifndef SU3_WAVES_PACK_R12
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64) void pack_r12(const u4 *__restrict__ src, u4 *_
     constexpr int kOut = sizeof(V) == 8 ? 3 : 6;   // output chunks per link
     __shared__ u4 stage[64 * 9];
     const int lane = threadIdx.x;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t nin = links * 9, nout = links * kOut;
     const bool whole = (t + 1) * 64 <= links;
     u4 v[9];
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64) void unpack_r12(const u4 *__restrict__ src, u4 
     constexpr int kIn = sizeof(V) == 8 ? 3 : 6;   // input chunks per link
     __shared__ u4 stage[64 * 9];
     const int lane = threadIdx.x;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t nin = links * kIn, nout = links * 9;
     const bool whole = (t + 1) * 64 <= links;
     u4 v[kIn];
@@ -247,16 +247,17 @@ __global__ __launch_bounds__(kCopyBlock) void stream_copy(const u4 *__restrict__
         st_stream(dst + i, ld_stream(src + i));
 }
 
-// Access-shape probe: wavefront w reads chunks w*64*RA + 64 i + lane of a
+// Access-shape probe: wavefront w (the workgroup index, or with order 1 its
+// XCD-contiguous tile, xcd_order) reads chunks w*64*RA + 64 i + lane of a
 // (i < RA) and likewise of b, and writes chunks w*64*W + 64 i + lane of c,
 // the same whole-wavefront 1 KiB runs and per-lane chunk counts as the
 // kernels it stands beside, with no arithmetic beyond folding the loads
 // into the stored values (so that no load is dead).
 template <int RA, int RB, int W>
 __global__ __launch_bounds__(64) void stream_shape(const u4 *__restrict__ a, const u4 *__restrict__ b,
-                                                   u4 *__restrict__ c)
+                                                   u4 *__restrict__ c, int order)
 {
-    const int64_t w = blockIdx.x;
+    const int64_t w = order ? xcd_order(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int lane = threadIdx.x;
     u4 va[RA], vb[RB > 0 ? RB : 1];
 #pragma unroll
@@ -319,29 +320,30 @@ bool stream_shape_supported(int in_a, int in_b, int out)
 }
 
 template <int RA, int RB, int W>
-static hipError_t launch_shape_k(const void *a, const void *b, void *c, int64_t tiles, int waves, hipStream_t s)
+static hipError_t launch_shape_k(const void *a, const void *b, void *c, int64_t tiles, int waves, int order,
+                                 hipStream_t s)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return hipErrorInvalidDevice;
     const size_t pad = occupancy_pad_for(reinterpret_cast<const void *>(stream_shape<RA, RB, W>), waves, 64, dev);
     return launch_k(stream_shape<RA, RB, W>, dim3((unsigned)tiles), dim3(64), s, pad, (const u4 *)a, (const u4 *)b,
-                    (u4 *)c);
+                    (u4 *)c, order);
 }
 
 hipError_t launch_stream_shape(const void *a, const void *b, void *c, int64_t tiles, int in_a, int in_b, int out,
-                               int waves_per_cu, hipStream_t s)
+                               int waves_per_cu, int tile_order, hipStream_t s)
 {
     if (in_a == 1 && in_b == 0 && out == 1)
-        return launch_shape_k<1, 0, 1>(a, b, c, tiles, waves_per_cu, s);
+        return launch_shape_k<1, 0, 1>(a, b, c, tiles, waves_per_cu, tile_order, s);
     if (in_a == 3 && in_b == 0 && out == 3)
-        return launch_shape_k<3, 0, 3>(a, b, c, tiles, waves_per_cu, s);
+        return launch_shape_k<3, 0, 3>(a, b, c, tiles, waves_per_cu, tile_order, s);
     if (in_a == 3 && in_b == 3 && out == 3)
-        return launch_shape_k<3, 3, 3>(a, b, c, tiles, waves_per_cu, s);
+        return launch_shape_k<3, 3, 3>(a, b, c, tiles, waves_per_cu, tile_order, s);
     if (in_a == 6 && in_b == 0 && out == 9)
-        return launch_shape_k<6, 0, 9>(a, b, c, tiles, waves_per_cu, s);
+        return launch_shape_k<6, 0, 9>(a, b, c, tiles, waves_per_cu, tile_order, s);
     if (in_a == 9 && in_b == 0 && out == 9)
-        return launch_shape_k<9, 0, 9>(a, b, c, tiles, waves_per_cu, s);
+        return launch_shape_k<9, 0, 9>(a, b, c, tiles, waves_per_cu, tile_order, s);
     return hipErrorInvalidValue;
 }
 

@@ -258,9 +258,11 @@ def mult_nn_bwd(a: torch.Tensor, b: torch.Tensor, dc: torch.Tensor) -> tuple[tor
 
 
 def stream_shape(a: torch.Tensor, b: torch.Tensor | None, c: torch.Tensor, in_a: int, in_b: int, out: int,
-                 waves_per_cu: int = 0) -> None:
+                 waves_per_cu: int = 0, tile_order: int = 0) -> None:
     """The streaming probe of an access shape (su3_stream_shape) over byte
-    buffers: a holds tiles*1024*in_a bytes, b tiles*1024*in_b, c tiles*1024*out."""
+    buffers: a holds tiles*1024*in_a bytes, b tiles*1024*in_b, c tiles*1024*out.
+    tile_order 0 gives workgroup i tile i, 1 the XCD-contiguous order of the
+    site-major products."""
     tiles = a.numel() * a.element_size() // (1024 * in_a)
     if (a.numel() * a.element_size() != tiles * 1024 * in_a or c.numel() * c.element_size() != tiles * 1024 * out
             or (in_b and (b is None or b.numel() * b.element_size() != tiles * 1024 * in_b))):
@@ -269,7 +271,7 @@ def stream_shape(a: torch.Tensor, b: torch.Tensor | None, c: torch.Tensor, in_a:
     _need_gpu(*ts)
     with torch.cuda.device(a.device):
         check(abi.su3_stream_shape(a.data_ptr(), b.data_ptr() if in_b else None, c.data_ptr(), tiles, in_a, in_b,
-                                   out, waves_per_cu, _stream(a)), "su3_stream_shape")
+                                   out, waves_per_cu, tile_order, _stream(a)), "su3_stream_shape")
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:

@@ -153,19 +153,21 @@ def test_stream_copy_validation(abi):
 
 def test_stream_shape_validation(abi):
     f = abi.su3_stream_shape
-    assert f(A, 0, C, 0, 3, 0, 3, 0, None) == abi.SU3_OK                 # nothing to do
-    assert f(A, 0, C, 4, 2, 0, 2, 0, None) == abi.SU3_ERR_SIZE           # not a kernel's shape
-    assert f(A, 0, C, -1, 3, 0, 3, 0, None) == abi.SU3_ERR_SIZE
-    assert f(A, 0, C, 4, 3, 0, 3, 33, None) == abi.SU3_ERR_SIZE
-    assert f(A, 0, C, 1 << 26, 3, 0, 3, 0, None) == abi.SU3_ERR_SIZE      # grid beyond 2^32 work-items
-    assert f(A, 0, C, (1 << 62) // 1024, 9, 0, 9, 0, None) == abi.SU3_ERR_SIZE   # sizes would overflow
-    assert f(A, 0, C, (1 << 63) - 1, 9, 0, 9, 0, None) == abi.SU3_ERR_SIZE      # so would the grid product
-    assert f(0, 0, C, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_NULL
-    assert f(A, 0, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_NULL           # b needed
-    assert f(A + 8, 0, C, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_ALIGN
-    assert f(A, B + 8, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_ALIGN
-    assert f(A, 0, A + 1024, 4, 3, 0, 3, 0, None) == abi.SU3_ERR_OVERLAP
-    assert f(A, C + 16, C, 4, 3, 3, 3, 0, None) == abi.SU3_ERR_OVERLAP
+    assert f(A, 0, C, 0, 3, 0, 3, 0, 0, None) == abi.SU3_OK                 # nothing to do
+    assert f(A, 0, C, 4, 2, 0, 2, 0, 0, None) == abi.SU3_ERR_SIZE           # not a kernel's shape
+    assert f(A, 0, C, -1, 3, 0, 3, 0, 0, None) == abi.SU3_ERR_SIZE
+    assert f(A, 0, C, 4, 3, 0, 3, 33, 0, None) == abi.SU3_ERR_SIZE
+    assert f(A, 0, C, 4, 3, 0, 3, 0, 2, None) == abi.SU3_ERR_SIZE       # tile order 0 or 1
+    assert f(A, 0, C, 4, 3, 0, 3, 0, -1, None) == abi.SU3_ERR_SIZE
+    assert f(A, 0, C, 1 << 26, 3, 0, 3, 0, 0, None) == abi.SU3_ERR_SIZE      # grid beyond 2^32 work-items
+    assert f(A, 0, C, (1 << 62) // 1024, 9, 0, 9, 0, 0, None) == abi.SU3_ERR_SIZE   # sizes would overflow
+    assert f(A, 0, C, (1 << 63) - 1, 9, 0, 9, 0, 0, None) == abi.SU3_ERR_SIZE      # so would the grid product
+    assert f(0, 0, C, 4, 3, 0, 3, 0, 0, None) == abi.SU3_ERR_NULL
+    assert f(A, 0, C, 4, 3, 3, 3, 0, 0, None) == abi.SU3_ERR_NULL           # b needed
+    assert f(A + 8, 0, C, 4, 3, 0, 3, 0, 0, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B + 8, C, 4, 3, 3, 3, 0, 0, None) == abi.SU3_ERR_ALIGN
+    assert f(A, 0, A + 1024, 4, 3, 0, 3, 0, 0, None) == abi.SU3_ERR_OVERLAP
+    assert f(A, C + 16, C, 4, 3, 3, 3, 0, 0, None) == abi.SU3_ERR_OVERLAP
 
 
 def test_launch_shape_rejects_before_hip(abi):

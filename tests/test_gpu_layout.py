@@ -62,14 +62,16 @@ def test_soa_matches_aos_at_l32(O, ops):
     assert d <= 1e-13
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("shape", [(1, 0, 1), (3, 0, 3), (3, 3, 3), (6, 0, 9), (9, 0, 9)])
-def test_stream_shape_pattern(ops, shape):
+def test_stream_shape_pattern(ops, shape, order):
     """The access-shape probe reads and writes exactly the chunks it
-    documents: chunk i of lane l of tile w holds the XOR of the lane's
-    loaded chunks with i added to its first word."""
+    documents, in either tile order: chunk i of lane l of tile w holds the
+    XOR of the lane's loaded chunks with i added to its first word. 7 tiles
+    leave 7 of the 8 XCDs one tile and the last none; 19 give 3, 3, 3, 2, ..."""
     in_a, in_b, out = shape
-    tiles = 7
-    say("stream shape %s tiles=%d" % (shape, tiles))
+    tiles = 7 if order == 0 else 19
+    say("stream shape %s tiles=%d order=%d" % (shape, tiles, order))
     rng = np.random.default_rng(sum(shape))
     a = rng.integers(0, 2 ** 32, size=(tiles, in_a, 64, 4), dtype=np.uint32)
     b = rng.integers(0, 2 ** 32, size=(tiles, max(in_b, 1), 64, 4), dtype=np.uint32)[:, :in_b]
@@ -79,7 +81,7 @@ def test_stream_shape_pattern(ops, shape):
     ta = to_dev(a.view(np.uint8).reshape(-1))
     tb = to_dev(np.ascontiguousarray(b).view(np.uint8).reshape(-1)) if in_b else None
     tc = torch.zeros(tiles * out * 1024, dtype=torch.uint8, device=ta.device)
-    ops.stream_shape(ta, tb, tc, in_a, in_b, out, waves_per_cu=8)
+    ops.stream_shape(ta, tb, tc, in_a, in_b, out, waves_per_cu=8, tile_order=order)
     got = tc.cpu().numpy().view(np.uint32).reshape(tiles, out, 64, 4)
     assert np.array_equal(got, want)
 
