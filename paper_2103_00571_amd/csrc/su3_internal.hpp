@@ -58,7 +58,9 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi)
 // x*q + min(x, r) + k (q = nb / 8, r = nb mod 8), so each XCD streams one
 // contiguous eighth of the buffers in address order instead of every eighth
 // tile. A bijection on [0, nb) for any nb: XCD x owns q tiles, plus one if
-// x < r.
+// x < r. The 8 is the XCD count of one device in the single-partition mode;
+// under another partitioning the order is still a bijection, so results do
+// not change, only the streaming rate may.
 constexpr int kXcds = 8;
 __device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t nb)
 {
