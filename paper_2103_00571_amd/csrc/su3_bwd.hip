@@ -53,6 +53,11 @@ constexpr int kBwdThreads = 64 * kBwdWaves;
 #ifndef SU3_BWD_WAVES_F32
 #define SU3_BWD_WAVES_F32 12
 #endif
+// Tile order of stage 1: 0, workgroup g takes tile group g; 1, the
+// XCD-contiguous order of the forward kernels (xcd_order).
+#ifndef SU3_BWD_XCD_ORDER
+#define SU3_BWD_XCD_ORDER 0
+#endif
 
 // FP64: unit = one row (3 complex, 48 B); 12 units per site.
 struct BwdF64 {
@@ -100,7 +105,9 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     u4 *stage = reinterpret_cast<u4 *>(scratch[wv]);
     double *red = reinterpret_cast<double *>(scratch[wv]);
-    const int64_t t0 = (int64_t)blockIdx.x * kBwdWaves * kTiles + wv;
+    // this workgroup's tile group; its partial goes to slot grp
+    const int64_t grp = SU3_BWD_XCD_ORDER ? xcd_order(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t t0 = grp * kBwdWaves * kTiles + wv;
     const int64_t nchunks = units * 3;
 
     if (threadIdx.x < 72)
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
         for (int w2 = 0; w2 < kBwdWaves; ++w2)
             for (int r = 3 * j; r < 3 * j + 3; ++r)
                 sum += rowsum[w2][18 * r + e];
-        ws[4 * ((int64_t)(threadIdx.x >> 2) * groups + blockIdx.x) + (threadIdx.x & 3)] = sum;
+        ws[4 * ((int64_t)(threadIdx.x >> 2) * groups + grp) + (threadIdx.x & 3)] = sum;
     }
 }
 
