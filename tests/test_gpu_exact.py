@@ -25,12 +25,15 @@ def ops():
 
 
 def _embed(z):
+    """Entry (k, l) = x + iy becomes the 2x2 block [[x, -y], [y, x]] at rows
+    2k, 2k+1 and columns 2l, 2l+1 (int64)."""
     x, y = np.rint(z.real).astype(np.int64), np.rint(z.imag).astype(np.int64)
-    blk = np.stack([np.stack([x, -y], -1), np.stack([y, x], -1)], -2)
-    nd = blk.ndim
-    order = list(range(nd - 4)) + [nd - 4, nd - 2, nd - 3, nd - 1]
-    sh = blk.shape
-    return blk.transpose(order).reshape(*sh[:-4], 2 * sh[-4], 2 * sh[-3])
+    out = np.empty(z.shape[:-2] + (2 * z.shape[-2], 2 * z.shape[-1]), dtype=np.int64)
+    out[..., 0::2, 0::2] = x
+    out[..., 0::2, 1::2] = -y
+    out[..., 1::2, 0::2] = y
+    out[..., 1::2, 1::2] = x
+    return out
 
 
 def _unembed(m):
@@ -61,6 +64,8 @@ def _same(got, want):
 
 
 def _bf16_same(got, want):
+    if isinstance(want, torch.Tensor):
+        want = want.cpu().numpy()
     want = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(want))).to(torch.float32).to(torch.bfloat16)
     return torch.equal(got.cpu().view(torch.int16), want.view(torch.int16))
 
@@ -153,3 +158,85 @@ def test_beyond_2_31_chunks(ops):
     sc = ops.mult_nn_soa(sa, tb)
     del sa
     assert _same(ops.soa_to_aos(sc)[tidx], want)
+
+
+def _grid_sizes(scale):
+    """Site counts whose tile counts (one workgroup per tile) take every
+    residue mod 8 for every kernel that deals tiles out XCD-contiguously:
+    16k+5 sites give ceil(s/16) = k+1 and ceil(3s/16) = 3k+1, 32k+7 give
+    ceil(s/32) = k+1 and ceil(3s/32) = 3k+1, 64k+11 give ceil(3s/64) = 3k+1,
+    over 8 consecutive k. `scale` (a multiple of 8) is added to k."""
+    return [m * (k + scale) + r for m, r in ((16, 5), (32, 7), (64, 11)) for k in range(8, 16)]
+
+
+def _check_all_products(ops, a, b, v, want, want12, want_na, want_an, want_mv, same):
+    """Every product and the reconstruct-12 pack and unpack against exact
+    expected values; same(got, want) compares bit for bit."""
+    tb32, tv32 = b.to(torch.complex64), v.to(torch.complex64)
+    assert same(ops.mult_nn(a, b), want)
+    assert same(ops.mult_nn(ops.pack(a, ops.SU3_F32), tb32), want)
+    assert _bf16_same(ops.mult_nn(ops.pack(a, ops.SU3_BF16), tb32), want)
+    p12, p12d = ops.pack(a, ops.SU3_R12_F32), ops.pack(a, ops.SU3_R12_F64)
+    assert same(p12, want12[:, :, :2, :]) and same(p12d, want12[:, :, :2, :])
+    assert same(ops.unpack(p12, ops.SU3_R12_F32), want12) and same(ops.unpack(p12d, ops.SU3_R12_F64), want12)
+    assert same(ops.mult_nn(ops.pack(a, ops.SU3_R12C_F32), tb32, form=ops.SU3_R12C_F32), want[:, :, :2, :])
+    for x, y, w in ((a, b, v), (a.to(torch.complex64), tb32, tv32)):
+        assert same(ops.mult_na(x, y), want_na)
+        assert same(ops.mult_an(x, y), want_an)
+        assert same(ops.mat_vec(x, w), want_mv)
+
+
+def test_every_grid_residue_exact(ops):
+    """The XCD-contiguous tile order maps workgroups onto tiles one to one for
+    every grid size: each product and the reconstruct-12 pack and unpack, on
+    grids of every residue mod 8, bit-exact against integer arithmetic, with
+    the workgroup counts checked."""
+    rng = np.random.default_rng(808)
+    seen = set()
+    for sites in _grid_sizes(0):
+        say("exact grid residues sites=%d" % sites)
+        grid, _ = ops.launch_shape(sites, ops.SU3_F64)
+        assert grid == -(-12 * sites // 64)
+        seen.add(grid % 8)
+        a, b, v = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3)), _ints(rng, (sites, 3))
+        A, B = _embed(a), _embed(b)[None]
+        V = _embed(v[:, None, :, None])[:, 0]
+        a12 = a.copy()
+        a12[:, :, 2, :] = _cross_row2(a)
+        # products whose results are written on the rebuilt links compare
+        # against a12 (the stored rows 0-1 and the rebuilt row 2)
+        _check_all_products(ops, to_dev(a), to_dev(b), to_dev(v), _unembed(A @ B), a12,
+                            _unembed(A @ _T(B)), _unembed(_T(A) @ B), _unembed(A @ V[:, None])[..., 0], _same)
+        w12 = _unembed(_embed(a12) @ B)
+        assert _same(ops.mult_nn(ops.pack(to_dev(a), ops.SU3_R12_F32), to_dev(b).to(torch.complex64)), w12)
+        assert _same(ops.mult_nn(ops.pack(to_dev(a), ops.SU3_R12_F64), to_dev(b)), w12)
+    assert seen == set(range(8))
+
+
+def test_every_grid_residue_exact_large(ops):
+    """The same on grids about 24,000 (FP64 forward) to 8,000 (reconstruct-12)
+    tiles long, every residue mod 8 again. The expected values come from
+    torch's complex128 products on the GPU, exact for these integer entries
+    (every partial sum is an integer far below 2^53)."""
+    rng = np.random.default_rng(809)
+    seen = set()
+    for sites in _grid_sizes(8000)[:16]:
+        say("exact grid residues sites=%d" % sites)
+        grid, _ = ops.launch_shape(sites, ops.SU3_F64)
+        seen.add(grid % 8)
+        a, b, v = (to_dev(_ints(rng, sh)) for sh in ((sites, 4, 3, 3), (4, 3, 3), (sites, 3)))
+        bh = b.conj().transpose(-1, -2).resolve_conj().contiguous()
+        ah = a.conj().transpose(-1, -2).resolve_conj().contiguous()
+        r0, r1 = a[:, :, 0, :], a[:, :, 1, :]
+        a12 = a.clone()
+        for p, (i, j) in enumerate(((1, 2), (2, 0), (0, 1))):
+            a12[:, :, 2, p] = torch.conj(r0[..., i] * r1[..., j] - r0[..., j] * r1[..., i])
+        want, want_mv = torch.matmul(a, b), torch.matmul(a, v[:, None, :, None])[..., 0]
+
+        def same(got, w):
+            return torch.equal(torch.view_as_real(got.to(torch.complex128)), torch.view_as_real(w))
+        _check_all_products(ops, a, b, v, want, a12, torch.matmul(a, bh), torch.matmul(ah, b), want_mv, same)
+        w12 = torch.matmul(a12, b)
+        assert same(ops.mult_nn(ops.pack(a, ops.SU3_R12_F32), b.to(torch.complex64)), w12)
+        assert same(ops.mult_nn(ops.pack(a, ops.SU3_R12_F64), b), w12)
+    assert seen == set(range(8))
