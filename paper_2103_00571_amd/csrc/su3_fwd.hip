@@ -13,7 +13,8 @@
 //    access of a wavefront is already one contiguous run, and the row is
 //    uniform over a workgroup, so b[j] sits in scalar registers (fwd_soa).
 //  * The grid covers the lattice once: each wavefront streams one tile and
-//    exits, and the dispatcher hands out tiles in address order.
+//    exits. In the site-major kernels each XCD takes one contiguous eighth of
+//    the tiles (xcd_tile); the SoA kernel keeps tile = workgroup index.
 //  * a and c are streamed with nontemporal 16-byte loads and stores.
 //  * 64-bit offsets throughout (a FP64 L=48 lattice is 3.06e9 bytes).
 #include "su3_internal.hpp"
