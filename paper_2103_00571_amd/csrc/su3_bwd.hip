@@ -209,12 +209,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
             stage[3 * lane + i] = __builtin_bit_cast(u4, w);
         }
         wave_sync_bwd();
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int64_t gi = g0 + 64 * i;
-            if (whole || gi < nchunks)
-                st_stream(da + gi, stage[64 * i + lane]);
-        }
+        store_runs<3>(da, stage, g0, lane, whole, nchunks);
         wave_sync_bwd();
     }
 

@@ -463,13 +463,7 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
     for (int i = 0; i < F::kOut; ++i)
         my[F::kOut * lane + i] = o[i];
     wave_sync();
-    const int64_t gout = t * 64 * F::kOut + lane;
-#pragma unroll
-    for (int i = 0; i < F::kOut; ++i) {
-        const int64_t g = gout + 64 * i;
-        if (whole || g < nout)
-            st_stream(c + g, my[64 * i + lane]);
-    }
+    store_runs<F::kOut>(c, my, t * 64 * F::kOut + lane, lane, whole, nout);
 }
 
 // ---------------------------------------------------------------- SoA

@@ -80,6 +80,32 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nb)
     return SU3_XCD_ORDER ? xcd_order(bid, nb) : bid;
 }
 
+// Store N whole-wavefront runs from a wavefront's LDS slice:
+// dst[base + 64 i] = slice[64 i + lane] for i < N, where base already holds
+// the lane's offset; positions at or past n are skipped unless the tile is
+// whole (wave-uniform). Every LDS read is issued before the first store, so
+// the wavefront waits for LDS once, and a whole tile stores without
+// branches.
+template <int N>
+__device__ __forceinline__ void store_runs(u4 *__restrict__ dst, const u4 *slice, int64_t base, int lane, bool whole,
+                                           int64_t n)
+{
+    u4 w[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        w[i] = slice[64 * i + lane];
+    if (whole) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            st_stream(dst + base + 64 * i, w[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (base + 64 * i < n)
+                st_stream(dst + base + 64 * i, w[i]);
+    }
+}
+
 // Threads per workgroup of the streaming kernels: four wave64s.
 constexpr int kBlock = 256;
 
