@@ -234,6 +234,7 @@ def main() -> int:
         bsites = args.bwd_L ** 4
         # (shape, tiles, tile order of the kernels beside it, kernels)
         shapes = [((3, 0, 3), 12 * sites // 64, 1, "f64, f32, bf16, r12c, na"),
+                  ((3, 0, 3), 12 * sites // 64, 0, "none (the same shape with tile = workgroup index)"),
                   ((1, 0, 1), 36 * sites // 64, 0, "copy"),
                   ((3, 3, 3), 12 * bsites // 64, 0, "bwd_f64, bwd_f32"),
                   ((6, 0, 9), 2 * sites // 64, 1, "r12, r12f64"),
@@ -255,6 +256,8 @@ def main() -> int:
                 if best is None or gbs > best[0]:
                     best = (gbs, cap, ms)
             key = "%d+%d in, %d out" % (ia, ib, io)
+            if key in res:
+                key += ", %s order" % ("xcd" if order else "index")
             res[key] = {"gb_s": best[0], "waves_per_cu": best[1], "ms": best[2], "bytes": nbytes,
                         "tile_order": "xcd" if order else "index", "kernels": beside}
             log("shape %-14s ceiling %7.1f GB/s (cap %d, %s order)  beside %s"

@@ -24,8 +24,8 @@
 // Stage 2 reduces the partials of each of the 72 real components in two
 // fixed-order levels: bwd_chunk_sums adds runs of kChunk consecutive partials
 // of a quad's 4 components (8 per thread, then a binary tree per component),
-// bwd_reduce adds the run sums, stored component-major (a strided
-// loop, then a binary tree). Both levels keep every load of a thread in
+// bwd_reduce adds the run sums, stored component-major (one wavefront per
+// component: a strided loop, then a binary tree across the lanes). Both levels keep every load of a thread in
 // flight at once, so stage 2 costs a few microseconds at any lattice size.
 // The number of workgroups of every stage depends only on the number of sites
 // and the form, so the rounding sequence, and every bit of dB, is the same on
@@ -265,17 +265,6 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     }
 }
 
-// Binary tree over red[0 .. kBlock) in a fixed order; the sum ends in red[0].
-__device__ __forceinline__ void block_tree(double *red)
-{
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-}
-
 // grid = (chunks, 18): workgroup (c, u) adds partials c*kChunk .. c*kChunk +
 // kChunk - 1 of the 4 components of quad u (thread t takes t, t + kBlock,
 // ... in order, then a tree per component) and writes run sums
@@ -318,21 +307,24 @@ __global__ __launch_bounds__(kBlock) void bwd_chunk_sums(const double *__restric
         ws2[(int64_t)(4 * blockIdx.y + threadIdx.x) * chunks + c] = red[threadIdx.x][0];
 }
 
-// grid = 72 workgroups, one per real component of dB; the input holds
-// `groups` values per component, component-major (the run sums of stage 2a)
-__global__ __launch_bounds__(kBlock) void bwd_reduce(const double *__restrict__ ws, double *__restrict__ db,
-                                                     int64_t groups)
+// grid = 72 workgroups of one wavefront, one per real component of dB; the
+// input holds `groups` values per component, component-major (the run sums
+// of stage 2a). Lane t adds values t, t + 64, ... in order, then a binary
+// tree across the lanes pairs lane t with t + w for w = 32, 16, ..., 1.
+__global__ __launch_bounds__(64) void bwd_reduce(const double *__restrict__ ws, double *__restrict__ db,
+                                                 int64_t groups)
 {
-    __shared__ double red[kBlock];
     const int q = blockIdx.x;
     double sum = 0.0;
-    for (int64_t g = threadIdx.x; g < groups; g += kBlock)
+    for (int64_t g = threadIdx.x; g < groups; g += 64)
         sum += ws[(int64_t)q * groups + g];
-    red[threadIdx.x] = sum;
-    block_tree(red);
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1)
+        sum += __shfl_down(sum, w, 64);
     if (threadIdx.x == 0)
-        db[q] = red[0];
+        db[q] = sum;
 }
+constexpr int kReduceThreads = 64;
 
 // Workgroups of stage 1 for `sites` (a function of the size and form only).
 int64_t bwd_groups(int64_t sites, int precision)
@@ -377,14 +369,14 @@ hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, do
                  chunks);
     if (e != hipSuccess)
         return e;
-    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)ws2, db, chunks);
+    return launch_k(bwd_reduce, dim3(72), dim3(kReduceThreads), s, 0, (const double *)ws2, db, chunks);
 }
 
 // An empty lattice has dB = 0: the second stage over zero partials writes
 // zeros (a kernel rather than a memset, so the call is safe to capture).
 hipError_t launch_bwd_zero(double *db, hipStream_t s)
 {
-    return launch_k(bwd_reduce, dim3(72), dim3(kBlock), s, 0, (const double *)nullptr, db, (int64_t)0);
+    return launch_k(bwd_reduce, dim3(72), dim3(kReduceThreads), s, 0, (const double *)nullptr, db, (int64_t)0);
 }
 
 } // namespace su3

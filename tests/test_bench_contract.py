@@ -19,6 +19,26 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in proc.stderr and proc.stdout == ""
 
 
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_kernel_hash_ignores_comments_and_layout_only():
+    """roofline.traffic is kept only while the kernel code matches the code
+    the counters were taken on: comments and whitespace do not count, code
+    does."""
+    b = _bench_module()
+    code = "int f(int x) {\n    return x + 1; // one more\n}\n"
+    assert b._code_only(code) == b._code_only("/* header */\nint f(int x)\n{ return x + 1;  }\n")
+    assert b._code_only(code) != b._code_only(code.replace("x + 1", "x + 2"))
+    assert b._code_only("a /* x\n y */ b // z\nc") == "a b c"
+    assert len(b.kernel_source_hash()) == 16
+
+
 @pytest.mark.gpu
 def test_one_json_line_with_the_contract_keys():
     print("[gpu] bench.py short run", flush=True)
