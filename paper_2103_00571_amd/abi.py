@@ -46,8 +46,8 @@ SIGNATURES = {
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            "libsu3.so is not built (%s); run `python -c 'import __graft_entry__ as g; g.build()'` "
-            "or `python -m paper_2103_00571_amd.build`" % LIB_PATH)
+            "libsu3.so is not built (%s); run `python -m paper_2103_00571_amd.build` "
+            "from the repository root" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in SIGNATURES.items():
         fn = getattr(lib, name)
