@@ -25,8 +25,9 @@
 // fixed-order levels: bwd_chunk_sums adds runs of kChunk consecutive partials
 // of a quad's 4 components (8 per thread, then a binary tree per component),
 // bwd_reduce adds the run sums, stored component-major (one wavefront per
-// component: a strided loop, then a binary tree across the lanes). Both levels keep every load of a thread in
-// flight at once, so stage 2 costs a few microseconds at any lattice size.
+// component: a strided loop, then a binary tree across the lanes). Both
+// levels keep every load of a thread in flight at once, so stage 2 costs a
+// few microseconds at any lattice size.
 // The number of workgroups of every stage depends only on the number of sites
 // and the form, so the rounding sequence, and every bit of dB, is the same on
 // every run and every device. No atomics.
