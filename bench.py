@@ -7,13 +7,17 @@ the FP64 site-major (AoS) product on an L=48 lattice (5,308,416 sites, 3.06 GB
 per array): W untimed passes, then K passes timed with HIP events on the
 stream the kernel runs on, bracketed by device synchronisation. `value` is
 sites per second. The other storage forms, the SoA layout, one GPU's share of
-the lattice split over 8 GPUs (shard8), the streaming copy over the same
+the lattice split over 8 GPUs (shard8), the L=32 lattice (FP64 and FP32,
+site-major and SoA, 100 timed passes), the streaming copy over the same
 footprint (the measured bandwidth reference) and the adjoint (L=32) are timed
 the same way and reported under "forms", with the streaming ceiling of each
 kernel's access shape (su3_stream_shape, "shapes").
 
 Inputs are seeded synthetic Haar SU(3) links (latgen), generated on the host
-and copied to HBM before timing starts. Prints one JSON line.
+and copied to HBM before timing starts. A short untimed streaming warm-up
+precedes the first timed region. The CPU baseline is the oracle on one pinned
+host core (a bounded sample) and, beside it, an OpenMP parallel-for over every
+host core. Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -23,6 +27,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -106,41 +111,92 @@ def traffic_record():
     return rec.get("traffic_bytes_per_launch")
 
 
+def host_info() -> dict:
+    """CPU model, core counts and NUMA node count of the host."""
+    info = {"cpu_model": "unknown", "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(),
+            "numa_nodes": None, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "Model name":
+                info["cpu_model"] = val
+            elif key in ("Socket(s)", "Core(s) per socket", "Thread(s) per core", "NUMA node(s)"):
+                info[key.lower().replace("(s)", "s").replace(" ", "_")] = int(val) if val.isdigit() else val
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if info["cpu_model"] == "unknown":
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        info["cpu_model"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    try:
+        info["numa_nodes"] = len([d for d in os.listdir("/sys/devices/system/node") if re.fullmatch(r"node\d+", d)])
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline_leg(a, b, sample_idx, seconds: float, L: int):
-    """The oracle (plain single-threaded C, FP64) timed on the host on a
-    bounded sample of the same workload, and its reference values on the
-    sampled sites used for the error report."""
+    """The oracle (plain single-threaded C, FP64) timed on one host core on
+    a bounded sample of the same workload -- the first 2^20 sites of the
+    lattice, which are exactly the L=32 lattice of the same seed -- and its
+    reference values on the sampled sites used for the error report."""
     import numpy as np
 
     import oracle
     O = oracle.default()
     sample = np.ascontiguousarray(a[: 1 << 20])
     O.mult_nn(sample[:1024], b)            # load and warm
-    passes, t0 = 0, time.perf_counter()
-    while True:
-        O.mult_nn(sample, b)
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    # pin this thread (the one that calls the oracle) to one core for the
+    # timing, then give it back its cores
+    os.sched_setaffinity(0, {core})
+    try:
+        passes, t0 = 0, time.perf_counter()
+        while True:
+            O.mult_nn(sample, b)
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    finally:
+        os.sched_setaffinity(0, allowed)
     rate = passes * sample.shape[0] / el
     ref = O.mult_nn(a[sample_idx], b)
     rec = {"value": rate, "unit": "sites/s", "cores": 1, "kind": "oracle",
-           "sample": "first %d sites of the L=%d lattice, FP64 AoS, %d passes in %.1f s, single thread"
-                     % (sample.shape[0], L, passes, el),
-           "gb_s": rate * 1152 / 1e9, "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+           "sample": "first %d sites of the L=%d lattice (the L=32 lattice of the same seed), FP64 AoS, "
+                     "%d passes in %.1f s, single thread pinned to CPU %d" % (sample.shape[0], L, passes, el, core),
+           "gb_s": rate * 1152 / 1e9, "pinned_cpu": core, "host": host_info()}
     return rec, ref, O
 
 
-def host_cpu_model() -> str:
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+def cpu_omp_leg(sites: int, seconds: float) -> dict:
+    """The multi-core CPU baseline: the product over `sites` sites on every
+    host core the process may use, one OpenMP parallel-for over sites with
+    parallel first-touch initialisation and close thread binding (the paper's
+    best Xeon setup), run as a child process. Returns its JSON record."""
+    import oracle
+    if not os.path.exists(oracle.CPU_OMP):
+        oracle.build(force=False)
+    env = dict(os.environ, OMP_PROC_BIND="close", OMP_PLACES="cores")
+    cmd = [oracle.CPU_OMP, str(sites), "2", "5", "%.1f" % seconds]
+    proc = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    if proc.returncode != 0:
+        return {"error": "exit %d: %s" % (proc.returncode, (proc.stdout + proc.stderr)[-500:])}
+    rec = json.loads(proc.stdout.strip().splitlines()[-1])
+    rec.update({"unit": "sites/s", "value": rec["sites_per_s"], "cores": rec["threads"],
+                "kind": "openmp parallel-for, all host cores (not the oracle)",
+                "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+                "sample": "the full %d-site lattice, FP64 AoS, paper's constant initialisation, parallel first touch"
+                          % sites})
+    return rec
 
 
 def main() -> int:
@@ -150,9 +206,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
-    ap.add_argument("--forms", default="f64,shard8,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,setup,copy,shapes,bwd")
+    ap.add_argument("--forms",
+                    default="f64,shard8,l32,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,setup,copy,shapes,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-omp", action="store_true", help="skip the multi-core OpenMP CPU baseline")
+    ap.add_argument("--cpu-omp-seconds", type=float, default=4.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -196,8 +255,20 @@ def main() -> int:
         log("%-5s %8.4f ms  %.3e sites/s  %7.1f GB/s  (%.1f%% of 8 TB/s)"
             % (name, ms, n_sites / (ms * 1e-3), gbs, 100 * gbs / HBM_PEAK_GBS))
 
-    # ---- headline: FP64 AoS ------------------------------------------------
+    # ---- device warm-up (untimed) --------------------------------------------
+    # About 0.2 s of the streaming copy over the headline's footprint, so that
+    # clocks and memory are in their steady state before the first timed
+    # region; the first dispatches on a cold device run several percent slow.
     c64 = torch.empty_like(ta)
+    t0w, nw = time.perf_counter(), 0
+    while time.perf_counter() - t0w < 0.2:
+        for _ in range(10):
+            ops.stream_copy(ta, c64)
+        torch.cuda.synchronize()
+        nw += 10
+    log("device warm-up: %d streaming copies in %.2f s" % (nw, time.perf_counter() - t0w))
+
+    # ---- headline: FP64 AoS ------------------------------------------------
     grid, block = ops.launch_shape(sites, ops.SU3_F64)
     ms64 = time_launches(lambda: ops.mult_nn(ta, tb64, out=c64), args.steps, args.warmup, torch)
     record("f64", ms64, BYTES_PER_SITE["f64"], sites)
@@ -213,6 +284,33 @@ def main() -> int:
         record("shard8", ms, BYTES_PER_SITE["f64"], ns)
         results["shard8"]["sites"] = ns
         del ys
+
+    # ---- the L=32 lattice (1,048,576 sites): 100 timed passes ----------------
+    # The first 2^20 sites of the lattice are the L=32 lattice of the same seed
+    # (entries are a function of the site index only). Site-major FP64 and
+    # FP32 and the SoA layout in both, each into a preallocated output.
+    n32 = 32 ** 4
+    steps32 = max(args.steps, 100)
+    if "l32" in forms and sites >= n32:
+        x64 = ta[:n32]
+        y64 = torch.empty_like(x64)
+        ms = time_launches(lambda: ops.mult_nn(x64, tb64, out=y64), steps32, args.warmup, torch)
+        record("f64_L32", ms, BYTES_PER_SITE["f64"], n32)
+        results["f64_L32"].update({"sites": n32, "steps": steps32})
+        x32 = ops.pack(x64, ops.SU3_F32)
+        y32 = torch.empty_like(x32)
+        ms = time_launches(lambda: ops.mult_nn(x32, tb32, out=y32), steps32, args.warmup, torch)
+        record("f32_L32", ms, BYTES_PER_SITE["f32"], n32)
+        results["f32_L32"].update({"sites": n32, "steps": steps32})
+        for name, x, tb, key in (("soa_L32", x64, tb64, "f64_L32"), ("soa32_L32", x32, tb32, "f32_L32")):
+            sa = ops.aos_to_soa(x)
+            sc = torch.empty_like(sa)
+            ms = time_launches(lambda: ops.mult_nn_soa(sa, tb, out=sc), steps32, args.warmup, torch)
+            record(name, ms, BYTES_PER_SITE["soa" if name == "soa_L32" else "soa32"], n32)
+            results[name].update({"sites": n32, "steps": steps32,
+                                  "vs_site_major": results[key]["ms"] / ms})
+            del sa, sc
+        del y64, x32, y32
 
     # ---- streaming copy over the same footprint (measured bandwidth) -------
     if "copy" in forms:
@@ -271,6 +369,7 @@ def main() -> int:
         sc = torch.empty_like(sa)
         ms = time_launches(lambda: ops.mult_nn_soa(sa, tb64, out=sc), args.steps, args.warmup, torch)
         record("soa", ms, BYTES_PER_SITE["soa"], sites)
+        results["soa"]["vs_site_major"] = ms64 / ms
         outputs["soa"] = ops.soa_to_aos(sc)
         del sa, sc
 
@@ -346,6 +445,8 @@ def main() -> int:
         sc = torch.empty_like(sa)
         record("soa32", time_launches(lambda: ops.mult_nn_soa(sa, tb32, out=sc), args.steps, args.warmup, torch),
                BYTES_PER_SITE["soa32"], sites)
+        if "f32" in results:
+            results["soa32"]["vs_site_major"] = results["f32"]["ms"] / results["soa32"]["ms"]
         del sa, sc
         y = torch.empty_like(t32)
         for name, fn in (("na32", ops.mult_na), ("an32", ops.mult_an)):
@@ -379,10 +480,16 @@ def main() -> int:
             xdc = torch.from_numpy(latgen.complex_normal_lattice(bs, seed=3)).to(dev)
             for name, dt, tb in (("bwd_f64", torch.complex128, tb64), ("bwd_f32", torch.complex64, tb32)):
                 xa_, xdc_ = xa.to(dt), xdc.to(dt)
-                ms = time_launches(lambda: ops.mult_nn_bwd(xa_, tb, xdc_), args.steps, args.warmup, torch)
+                # preallocated outputs and workspace, as in the forward legs
+                da_, db_ = torch.empty_like(xa_), torch.empty((4, 3, 3), dtype=torch.complex128, device=dev)
+                ws_ = ops.mult_nn_bwd_workspace(bs, ops.form_of(xa_), dev)
+                ms = time_launches(lambda: ops.mult_nn_bwd(xa_, tb, xdc_, da=da_, db=db_, ws=ws_), args.steps,
+                                   args.warmup, torch)
                 nb = BWD_BYTES_PER_SITE[name[4:]] * bs
                 results[name] = {"ms": ms, "sites_per_s": bs / (ms * 1e-3), "gb_s": nb / (ms * 1e-3) / 1e9,
-                                 "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "L": args.bwd_L}
+                                 "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "L": args.bwd_L,
+                                 "workspace_bytes": ws_.numel()}
+                del da_, db_, ws_
                 log("%-7s %8.4f ms  %.3e sites/s  %7.1f GB/s" % (name, ms, bs / (ms * 1e-3), nb / (ms * 1e-3) / 1e9))
             del xa, xdc
 
@@ -393,6 +500,18 @@ def main() -> int:
                                         [0, sites - 1]]))
         cpu, ref, O = cpu_baseline_leg(a, b, idx, args.cpu_seconds, L)
         log("oracle on host: %.3e sites/s (%s)" % (cpu["value"], cpu["sample"]))
+        if "f64_L32" in results:
+            # the oracle ran on exactly the L=32 lattice the GPU leg timed
+            results["f64_L32"]["oracle_sites_per_s"] = cpu["value"]
+            results["f64_L32"]["speedup_vs_oracle"] = results["f64_L32"]["sites_per_s"] / cpu["value"]
+        if not args.no_cpu_omp:
+            omp = cpu_omp_leg(sites, args.cpu_omp_seconds)
+            cpu["openmp_all_cores"] = omp
+            if "value" in omp:
+                log("openmp on %d host threads: %.3e sites/s, %.1f GB/s" % (omp["threads"], omp["value"],
+                                                                           omp["gb_s"]))
+            else:
+                log("openmp baseline failed: %s" % omp.get("error"))
         tidx = torch.from_numpy(idx).to(dev)
         for name, out in outputs.items():
             if name == "bf16":

@@ -20,7 +20,10 @@
  *    returns. No call allocates memory, synchronises, or keeps pointers after
  *    returning. The caller owns every buffer.
  *  - `sites` is the number of lattice sites (L^4 for an L^4 lattice).
- *    sites == 0 is valid and launches nothing.
+ *    sites == 0 is valid and launches nothing, with one exception: the
+ *    adjoint (su3_mult_nn_bwd) must still write db = 0, so for sites == 0 it
+ *    enqueues one small kernel that zeroes the 72 doubles of db_f64 (a
+ *    kernel, not a memset, so the call stays safe to capture in a graph).
  *  - Complex numbers are interleaved (re, im). A link is row-major 3x3:
  *    element (k, l) at complex offset 3k + l.
  *  - Site-major ("AoS") layout: link j of site s at complex offset
@@ -142,17 +145,23 @@ int su3_mat_vec(const void *a, const void *v, void *w, int64_t sites,
 
 /*
  * The same product on the SoA layout: a and c are 36 planes of `sites`
- * complex elements. Supports SU3_F64 and SU3_F32 (other forms return
- * SU3_ERR_PRECISION). Same alignment, overlap and error rules as
- * su3_mult_nn.
+ * complex elements. The paper names remapping the data structures as the
+ * main step in tuning SU3_Bench for wide SIMD machines (arXiv 2103.00571,
+ * section Related Work); the SoA layout is that remapping, with every plane
+ * access of a wavefront one contiguous run. Supports SU3_F64 and SU3_F32
+ * (other forms return SU3_ERR_PRECISION). Same alignment, overlap and error
+ * rules as su3_mult_nn.
  */
 int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites,
                     int precision, void *stream);
 
 /*
  * Layout transforms between AoS and SoA for SU3_F64 and SU3_F32 (a pure
- * permutation of complex elements, bit-exact). src and dst must not overlap
- * and must be 16-byte aligned.
+ * permutation of complex elements, bit-exact): the data-structure remapping
+ * of arXiv 2103.00571, section Related Work, as an explicit step outside the
+ * product. src and dst must not overlap and must be 16-byte aligned.
+ * Errors: SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION,
+ * SU3_ERR_OVERLAP, SU3_ERR_HIP.
  */
 int su3_aos_to_soa(const void *src, void *dst, int64_t sites, int precision,
                    void *stream);
@@ -160,7 +169,10 @@ int su3_soa_to_aos(const void *src, void *dst, int64_t sites, int precision,
                    void *stream);
 
 /*
- * Conversion from FP64 AoS links to a storage form, and back.
+ * Conversion from FP64 AoS links to a storage form, and back. The paper has
+ * no such step (its benchmark stores one precision); these entries belong to
+ * the library's reduced storage forms, which cut the bytes the product
+ * streams per site.
  *  su3_pack:   src is FP64 AoS; dst is the `precision` form of a
  *              (SU3_F32: round to nearest even; SU3_BF16: round to FP32, then
  *              to BF16, each to nearest even; SU3_R12_F32 and SU3_R12C_F32:
@@ -172,6 +184,8 @@ int su3_soa_to_aos(const void *src, void *dst, int64_t sites, int precision,
  *              as conj(row0 x row1) from the widened rows, each product and
  *              difference rounded separately (no fused multiply-add).
  * Both are bit-exact functions of their input.
+ * Errors: SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION,
+ * SU3_ERR_OVERLAP, SU3_ERR_HIP.
  */
 int su3_pack(const void *src_f64_aos, void *dst, int64_t sites, int precision,
              void *stream);
@@ -179,7 +193,10 @@ int su3_unpack(const void *src, void *dst_f64_aos, int64_t sites, int precision,
                void *stream);
 
 /*
- * Adjoint of su3_mult_nn for SU3_F64 and SU3_F32 (AoS). For the real loss
+ * Adjoint of su3_mult_nn for SU3_F64 and SU3_F32 (AoS). The paper has no
+ * adjoint; these are the two contractions that differentiate its product
+ * (section Background, subsection SU3_Bench), added so that the product can
+ * sit inside a differentiable program. For the real loss
  * Re sum conj(dc) * c, in the complex-gradient convention
  * dL/dRe(x) + i dL/dIm(x):
  *   da[s][j](k, m) = sum_l dc[s][j](k, l) * conj(b[j](m, l))      (dc b^H)
@@ -191,6 +208,7 @@ int su3_unpack(const void *src, void *dst_f64_aos, int64_t sites, int precision,
  * su3_mult_nn_bwd_workspace_bytes(sites, precision) bytes, 16-byte aligned,
  * owned by the caller, contents undefined on entry and exit.
  * da must not overlap a, b or dc; db_f64 and ws must not overlap anything.
+ * sites == 0: a, b, dc, da and ws may be NULL; one kernel writes db = 0.
  * Errors: as su3_mult_nn, plus SU3_ERR_WORKSPACE.
  */
 size_t su3_mult_nn_bwd_workspace_bytes(int64_t sites, int precision);

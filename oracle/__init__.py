@@ -22,6 +22,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "su3_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The multi-core CPU baseline (not the oracle): an OpenMP program that times
+# the product on every host core, run as a child process by the benchmark.
+_OMP_SRC = os.path.join(_HERE, "su3_cpu_omp.c")
+CPU_OMP = os.path.join(_HERE, "su3_cpu_omp")
+# x86-64-v3 (AVX2, FMA): any host CPU this runs on has it
+OMP_CFLAGS = ["-O3", "-std=c11", "-march=x86-64-v3", "-fopenmp"]
 
 # -ffp-contract=off: no fused multiply-add, so every rounding is the one the
 # source spells out. No -ffast-math.
@@ -32,11 +38,16 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc. Returns its path."""
+    """Compile liboracle.so, and the multi-core baseline program beside it,
+    with gcc. Returns the library's path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(CPU_OMP):
+        tmp = CPU_OMP + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *OMP_CFLAGS, _OMP_SRC, "-o", tmp], check=True)
+        os.replace(tmp, CPU_OMP)
     return _LIB
 
 

@@ -4,8 +4,11 @@
 //
 // With b[j] = I every product is an exact copy, so the program can check its
 // results without any reference implementation: c must equal a bit for bit,
-// and dA = dC b^H must equal dC bit for bit. Exit status 0 and "ok" on
-// success; the status string of the failing call otherwise.
+// and dA = dC b^H must equal dC bit for bit. The entries of a and dC are
+// small integers, so every partial sum of dB = sum_s a^H dC is an integer
+// below 2^53 and exact in FP64: dB must equal the same sum formed in int64
+// on the host. Exit status 0 and "ok" on success; the status string of the
+// failing call otherwise.
 //
 //   su3_c_api [sites]          (default 100003)
 #include <hip/hip_runtime_api.h>
@@ -92,9 +95,30 @@ int main(int argc, char **argv)
         std::fprintf(stderr, "dA != dC for b = I\n");
         return 6;
     }
+    // dB[j](m, l) = sum_s sum_k conj(a[s][j](k, m)) dC[s][j](k, l), in int64
+    std::vector<int64_t> want(72, 0);
+    for (int64_t s = 0; s < sites; ++s)
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 3; ++k)
+                for (int m = 0; m < 3; ++m)
+                    for (int l = 0; l < 3; ++l) {
+                        const size_t ia = 2 * (size_t)(((s * 4 + j) * 3 + k) * 3 + m);
+                        const size_t ig = 2 * (size_t)(((s * 4 + j) * 3 + k) * 3 + l);
+                        const int64_t ar = (int64_t)a[ia], ai = (int64_t)a[ia + 1];
+                        const int64_t gr = (int64_t)dc[ig], gi = (int64_t)dc[ig + 1];
+                        want[2 * (9 * j + 3 * m + l)] += ar * gr + ai * gi;
+                        want[2 * (9 * j + 3 * m + l) + 1] += ar * gi - ai * gr;
+                    }
+    std::vector<double> db(72);
+    HIP_OK(hipMemcpy(db.data(), d_db, 72 * sizeof(double), hipMemcpyDeviceToHost));
+    for (int q = 0; q < 72; ++q)
+        if (db[q] != (double)want[q]) {
+            std::fprintf(stderr, "dB[%d] = %.17g, exact sum %lld\n", q, db[q], (long long)want[q]);
+            return 7;
+        }
     for (void *p : {(void *)d_a, (void *)d_b, (void *)d_c, (void *)d_dc, (void *)d_da, (void *)d_db, d_ws})
         HIP_OK(hipFree(p));
     HIP_OK(hipStreamDestroy(stream));
-    std::printf("ok: %lld sites, forward and adjoint through the C ABI\n", (long long)sites);
+    std::printf("ok: %lld sites, forward and adjoint (dA and dB) through the C ABI\n", (long long)sites);
     return 0;
 }

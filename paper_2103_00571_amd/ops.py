@@ -28,7 +28,8 @@ from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, SU3_R12_F64, SU3_R12C_
 __all__ = [
     "SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32", "SU3_R12C_F32", "SU3_R12_F64",
     "form_of", "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack",
-    "mult_nn_bwd", "stream_copy", "stream_shape", "SU3MultNN", "mult_nn_autograd", "launch_shape",
+    "mult_nn_bwd", "mult_nn_bwd_workspace", "stream_copy", "stream_shape", "SU3MultNN", "mult_nn_autograd",
+    "launch_shape",
 ]
 
 _B_DTYPE = {SU3_F64: torch.complex128, SU3_F32: torch.complex64, SU3_BF16: torch.complex64,
@@ -236,9 +237,18 @@ def unpack(x: torch.Tensor, form: int | None = None) -> torch.Tensor:
     return out
 
 
-def mult_nn_bwd(a: torch.Tensor, b: torch.Tensor, dc: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:
+def mult_nn_bwd_workspace(sites: int, form: int, device: torch.device | int | None = None) -> torch.Tensor:
+    """A workspace tensor large enough for mult_nn_bwd on `sites` sites."""
+    nbytes = abi.su3_mult_nn_bwd_workspace_bytes(sites, form)
+    return torch.empty(max(nbytes, 16), dtype=torch.uint8, device=device)
+
+
+def mult_nn_bwd(a: torch.Tensor, b: torch.Tensor, dc: torch.Tensor, da: torch.Tensor | None = None,
+                db: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
     """Adjoint: returns (da, db64) with da = dc b^H per site (dtype of a) and
-    db64 = sum_s a^H dc as complex128 (4, 3, 3), deterministic."""
+    db64 = sum_s a^H dc as complex128 (4, 3, 3), deterministic. da, db and the
+    workspace ws (uint8, at least su3_mult_nn_bwd_workspace_bytes) may be
+    passed in; whatever is missing is allocated with torch.empty."""
     form = form_of(a)
     if form not in (SU3_F64, SU3_F32):
         raise ValueError("the adjoint exists for FP64 and FP32")
@@ -246,10 +256,18 @@ def mult_nn_bwd(a: torch.Tensor, b: torch.Tensor, dc: torch.Tensor) -> tuple[tor
     if dc.dtype != a.dtype or dc.shape != a.shape:
         raise ValueError("dc must match a in dtype and shape")
     sites = a.shape[0]
-    da = torch.empty_like(a)
-    db = torch.empty((4, 3, 3), dtype=torch.complex128, device=a.device)
-    nbytes = abi.su3_mult_nn_bwd_workspace_bytes(sites, form)
-    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=a.device)
+    if da is None:
+        da = torch.empty_like(a)
+    elif da.dtype != a.dtype or da.shape != a.shape:
+        raise ValueError("da must match a in dtype and shape")
+    if db is None:
+        db = torch.empty((4, 3, 3), dtype=torch.complex128, device=a.device)
+    elif db.dtype != torch.complex128 or tuple(db.shape) != (4, 3, 3):
+        raise ValueError("db must be complex128 of shape (4, 3, 3)")
+    if ws is None:
+        ws = mult_nn_bwd_workspace(sites, form, a.device)
+    elif ws.dtype != torch.uint8 or ws.dim() != 1:
+        raise ValueError("ws must be a 1-D uint8 tensor")
     _need_gpu(a, b, dc, da, db, ws)
     with torch.cuda.device(a.device):
         check(abi.su3_mult_nn_bwd(a.data_ptr(), b.data_ptr(), dc.data_ptr(), da.data_ptr(), db.data_ptr(), sites,

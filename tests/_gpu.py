@@ -2,6 +2,7 @@
 poisoned outputs with guard regions, and case labels printed before each GPU
 step."""
 
+import functools
 import sys
 
 import numpy as np
@@ -36,6 +37,18 @@ def poisoned(shape, dtype):
     return whole[GUARD:GUARD + shape[0]], whole
 
 
+def poison_(t):
+    """Fill t in place with NaN (BF16: the 0x7FC1 quiet-NaN pattern), so that
+    any output element a kernel fails to write shows up."""
+    if t.dtype == torch.bfloat16:
+        t.view(torch.int16).fill_(0x7FC1)
+    elif t.dtype.is_complex:
+        torch.view_as_real(t).fill_(float("nan"))
+    else:
+        t.fill_(float("nan"))
+    return t
+
+
 def guards_intact(whole):
     g = torch.cat([whole[:GUARD].reshape(-1), whole[-GUARD:].reshape(-1)])
     if g.dtype == torch.bfloat16:
@@ -56,8 +69,16 @@ def bf16_bits(t):
     return t.contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
 
 
-def sample_sites(sites, count, seed=0):
-    """Sorted distinct site indices: first, last, and `count` random ones."""
-    rng = np.random.default_rng(seed)
-    s = rng.choice(sites, size=min(count, sites), replace=False)
-    return np.unique(np.concatenate([s, [0, sites - 1]]))
+L48 = 48 ** 4
+
+
+@functools.lru_cache(maxsize=1)
+def l48_case():
+    """The benchmark's L=48 lattice (5,308,416 sites; a from seed 1, b from
+    seed 2) and the oracle's FP64 product of the two, built once per session
+    (3.06 GB each on the host)."""
+    import latgen
+    import oracle
+    a = latgen.random_lattice(L48, seed=1)
+    b = latgen.random_b(seed=2)
+    return a, b, oracle.default().mult_nn(a, b)

@@ -43,7 +43,8 @@ def test_kernel_hash_ignores_comments_and_layout_only():
 def test_one_json_line_with_the_contract_keys():
     print("[gpu] bench.py short run", flush=True)
     proc = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1", "--L",
-                           "16", "--bwd-L", "8", "--forms", "f64,copy,shapes,bwd", "--cpu-seconds", "0.5"],
+                           "16", "--bwd-L", "8", "--forms", "f64,copy,shapes,bwd", "--cpu-seconds", "0.5",
+                           "--cpu-omp-seconds", "0.5"],
                           capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert proc.returncode == 0, proc.stderr[-2000:]
     lines = [l for l in proc.stdout.splitlines() if l.strip()]
@@ -60,3 +61,7 @@ def test_one_json_line_with_the_contract_keys():
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0 and c["sample"]
+    assert c["host"]["nproc"] >= 1 and c["host"]["cpu_model"]
+    omp = c["openmp_all_cores"]
+    assert omp["check_ok"] is True and omp["threads"] >= 1 and omp["value"] > 0
+    assert omp["omp_proc_bind"] == "close" and omp["omp_places"] == "cores"

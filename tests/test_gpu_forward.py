@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import latgen
-from _gpu import all_finite, dev, guards_intact, poisoned, sample_sites, say, to_dev
+from _gpu import L48, all_finite, dev, guards_intact, l48_case, poisoned, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -112,18 +112,22 @@ def test_l32_full_parity(O, ops):
     assert O.max_abs_diff(c, O.mult_nn(a, b)) <= TOL64
 
 
-def test_l48_sampled_parity_and_closure(O, ops):
+def test_l48_full_parity_and_closure(O, ops):
     """L=48, 5,308,416 sites, in the launch configuration the benchmark times:
-    20,000 sampled sites against the oracle, and SU(3) closure of every
-    output (unitarity and det to 1e-13)."""
-    sites = 48 ** 4
+    every output, written into a NaN-poisoned buffer with guard sites, against
+    the oracle at 1e-13, and SU(3) closure of every output (unitarity and det
+    to 1e-13)."""
+    sites = L48
     grid, block = ops.launch_shape(sites, ops.SU3_F64)
-    say("fwd f64 L=48 sampled parity grid=%d block=%d" % (grid, block))
-    a = latgen.random_lattice(sites, seed=1)
-    b = latgen.random_b(seed=2)
-    c = ops.mult_nn(to_dev(a), to_dev(b)).cpu().numpy()
-    idx = sample_sites(sites, 20000, seed=48)
-    assert O.max_abs_diff(c[idx], O.mult_nn(a[idx], b)) <= TOL64
+    say("fwd f64 L=48 full parity grid=%d block=%d" % (grid, block))
+    a, b, ref = l48_case()
+    out, whole = poisoned((sites, 4, 3, 3), torch.complex128)
+    ops.mult_nn(to_dev(a), to_dev(b), out=out)
+    torch.cuda.synchronize()
+    assert guards_intact(whole)
+    c = out.cpu().numpy()
+    del out, whole
+    assert O.max_abs_diff(c, ref) <= TOL64
     assert O.unitarity_dev(c) <= 1e-13
     assert O.det_dev(c) <= 1e-13
 

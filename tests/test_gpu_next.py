@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import latgen
-from _gpu import all_finite, guards_intact, poisoned, sample_sites, say, to_dev
+from _gpu import L48, all_finite, guards_intact, l48_case, poison_, poisoned, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -167,54 +167,65 @@ def test_mat_vec_exact_pins(O, ops):
     assert np.array_equal(w, a[:, :, :, 1])
 
 
-def test_mat_vec_l48_sampled(O, ops):
-    sites = 48 ** 4
-    say("mat_vec L=48 sampled")
-    a, _ = _case(sites, 1)
+def test_mat_vec_l48_full(O, ops):
+    """L=48 matrix x colour vector: every output, written into a NaN-poisoned
+    buffer with guard sites, against the oracle at 1e-13."""
+    sites = L48
+    say("mat_vec L=48 full")
+    a, _, _ = l48_case()
     v = _vec(sites, 3)
-    w = ops.mat_vec(to_dev(a), to_dev(v))
-    idx = sample_sites(sites, 20000, seed=7)
-    got = w[torch.from_numpy(idx).to(w.device)].cpu().numpy()
-    assert O.max_abs_diff(got, O.mat_vec(a[idx], v[idx])) <= 1e-13
+    out, whole = poisoned((sites, 4, 3), torch.complex128)
+    ops.mat_vec(to_dev(a), to_dev(v), out=out)
+    torch.cuda.synchronize()
+    assert guards_intact(whole)
+    assert O.max_abs_diff(out.cpu().numpy(), O.mat_vec(a, v)) <= 1e-13
 
 
-def test_l48_products_sampled(O, ops):
+def test_l48_products_full(O, ops):
     """L=48 (5,308,416 sites), the inputs and launch configuration the
     benchmark times: a b^H, a^H b, reconstruct-12 in and out, reconstruct-12
     in FP64, the SoA product, and the FP64 product on one GPU's share of the
-    lattice split over 8 GPUs (the first 663,552 sites), each on 20,000
-    sampled sites against the oracle."""
-    sites = 48 ** 4
-    a, b = _case(sites, 1)
+    lattice split over 8 GPUs (the first 663,552 sites). Every output is
+    written into a NaN-poisoned buffer (with guard sites where the layout is
+    site-major) and compared with the oracle."""
+    sites = L48
+    a, b, ref = l48_case()
     ta, tb = to_dev(a), to_dev(b)
-    idx = sample_sites(sites, 20000, seed=11)
-    tidx = torch.from_numpy(idx).to(ta.device)
 
-    def sampled(c):
-        return c[tidx].cpu().numpy().astype(np.complex128 if c.dtype == torch.complex128 else np.complex64)
+    def run(fn, shape, dtype):
+        out, whole = poisoned(shape, dtype)
+        fn(out)
+        torch.cuda.synchronize()
+        assert guards_intact(whole)
+        return out.cpu().numpy()
 
+    full = (sites, 4, 3, 3)
     say("L=48 a b^H")
-    assert O.max_abs_diff(sampled(ops.mult_na(ta, tb)), O.mult_na(a[idx], b)) <= 1e-13
+    got = run(lambda o: ops.mult_na(ta, tb, out=o), full, torch.complex128)
+    assert O.max_abs_diff(got, O.mult_na(a, b)) <= 1e-13
     say("L=48 a^H b")
-    assert O.max_abs_diff(sampled(ops.mult_an(ta, tb)), O.mult_an(a[idx], b)) <= 1e-13
-    ref = O.mult_nn(a[idx], b)
+    got = run(lambda o: ops.mult_an(ta, tb, out=o), full, torch.complex128)
+    assert O.max_abs_diff(got, O.mult_an(a, b)) <= 1e-13
     say("L=48 reconstruct-12 FP64")
-    assert O.max_abs_diff(sampled(ops.mult_nn(ops.pack(ta, ops.SU3_R12_F64), tb)), ref) <= 1e-13
+    x = ops.pack(ta, ops.SU3_R12_F64)
+    got = run(lambda o: ops.mult_nn(x, tb, out=o), full, torch.complex128)
+    del x
+    assert O.max_abs_diff(got, ref) <= 1e-13
     say("L=48 reconstruct-12 in and out")
     b32 = to_dev(O.round_f32(b))
-    c12 = ops.mult_nn(ops.pack(ta, ops.SU3_R12C_F32), b32, form=ops.SU3_R12C_F32)
-    got = sampled(c12).astype(np.complex128)
-    del c12
-    assert O.max_abs_diff(got, np.ascontiguousarray(ref[:, :, :2, :])) <= 1e-5
+    x = ops.pack(ta, ops.SU3_R12C_F32)
+    got = run(lambda o: ops.mult_nn(x, b32, out=o, form=ops.SU3_R12C_F32), (sites, 4, 2, 3), torch.complex64)
+    del x
+    assert O.max_abs_diff(got.astype(np.complex128), np.ascontiguousarray(ref[:, :, :2, :])) <= 1e-5
     say("L=48 SoA")
-    csoa = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(ta), tb))
-    got = sampled(csoa)
-    del csoa
+    sa = ops.aos_to_soa(ta)
+    sc = poison_(torch.empty_like(sa))
+    ops.mult_nn_soa(sa, tb, out=sc)
+    del sa
+    got = ops.soa_to_aos(sc).cpu().numpy()
+    del sc
     assert O.max_abs_diff(got, ref) <= 1e-13
     say("L=48 / 8 share")
     ns = sites // 8
-    cs = ops.mult_nn(ta[:ns], tb)
-    sidx = idx[idx < ns]
-    assert sidx.size > 1000
-    got = cs[torch.from_numpy(sidx).to(cs.device)].cpu().numpy()
-    assert O.max_abs_diff(got, O.mult_nn(a[sidx], b)) <= 1e-13
+    got = run(lambda o: ops.mult_nn(ta[:ns], tb, out=o), (ns, 4, 3, 3), torch.complex128)
+    assert O.max_abs_diff(got, ref[:ns]) <= 1e-13
