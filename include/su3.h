@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define SU3_ABI_VERSION 4
+#define SU3_ABI_VERSION 5
 
 /* storage form codes */
 enum su3_precision {
@@ -215,6 +215,28 @@ size_t su3_mult_nn_bwd_workspace_bytes(int64_t sites, int precision);
 int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da,
                     double *db_f64, int64_t sites, int precision, void *ws,
                     size_t ws_bytes, void *stream);
+
+/*
+ * Allocation-free variant of su3_mult_nn_bwd, for callers that cannot
+ * allocate device memory or pass a workspace: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The workspace is a
+ * fixed array of SU3_BWD_SCRATCH_BYTES (64 MiB) in the library's device
+ * memory, one per device, kept until the process ends; the call itself
+ * allocates nothing. Arguments, results (bit for bit) and errors are those of
+ * su3_mult_nn_bwd without ws and ws_bytes, except that SU3_ERR_WORKSPACE
+ * means the lattice needs more workspace than the array holds:
+ * su3_mult_nn_bwd_workspace_bytes(sites, precision) > SU3_BWD_SCRATCH_BYTES,
+ * i.e. above about 7.4 million sites in FP64 and 14.9 million in FP32 (an
+ * L = 48 lattice, 5,308,416 sites, fits in both). The array's device address
+ * is looked up on the first call on each device, so make that first call
+ * outside graph capture. Every call on a device shares that device's array:
+ * calls that can overlap in time on one device (two streams, two host
+ * threads, two graphs) race on it and must be ordered by the caller.
+ */
+#define SU3_BWD_SCRATCH_BYTES ((size_t)64 << 20)
+int su3_mult_nn_bwd_noalloc(const void *a, const void *b, const void *dc, void *da,
+                            double *db_f64, int64_t sites, int precision,
+                            void *stream);
 
 /*
  * Measurement aid: device-to-device copy of `bytes` bytes, one 16-byte

@@ -15,11 +15,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsu3.so")
 
 # su3.h constants
-ABI_VERSION = 4
+ABI_VERSION = 5
 SU3_F64, SU3_F32, SU3_BF16, SU3_R12_F32, SU3_R12C_F32, SU3_R12_F64 = 0, 1, 2, 3, 4, 5
 SU3_OK = 0
 SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION = -1, -2, -3, -4
 SU3_ERR_OVERLAP, SU3_ERR_WORKSPACE, SU3_ERR_HIP = -5, -6, -7
+SU3_BWD_SCRATCH_BYTES = 64 << 20   # workspace of su3_mult_nn_bwd_noalloc
 
 # every symbol su3.h declares, with (argtypes, restype)
 _P, _I64, _I, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
@@ -37,6 +38,7 @@ SIGNATURES = {
     "su3_unpack": ([_P, _P, _I64, _I, _P], _I),
     "su3_mult_nn_bwd_workspace_bytes": ([_I64, _I], _SZ),
     "su3_mult_nn_bwd": ([_P, _P, _P, _P, _P, _I64, _I, _P, _SZ, _P], _I),
+    "su3_mult_nn_bwd_noalloc": ([_P, _P, _P, _P, _P, _I64, _I, _P], _I),
     "su3_stream_copy": ([_P, _P, _I64, _P], _I),
     "su3_stream_shape": ([_P, _P, _P, _I64, _I, _I, _I, _I, _I, _P], _I),
     "su3_launch_shape": ([_I64, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)], _I),
@@ -130,6 +132,11 @@ def su3_mult_nn_bwd_workspace_bytes(sites: int, precision: int) -> int:
 def su3_mult_nn_bwd(a: int, b: int, dc: int, da: int, db_f64: int, sites: int, precision: int,
                     ws: int, ws_bytes: int, stream: int) -> int:
     return lib.su3_mult_nn_bwd(a, b, dc, da, db_f64, sites, precision, ws, ws_bytes, stream)
+
+
+def su3_mult_nn_bwd_noalloc(a: int, b: int, dc: int, da: int, db_f64: int, sites: int, precision: int,
+                            stream: int) -> int:
+    return lib.su3_mult_nn_bwd_noalloc(a, b, dc, da, db_f64, sites, precision, stream)
 
 
 def su3_stream_copy(src: int, dst: int, nbytes: int, stream: int) -> int:

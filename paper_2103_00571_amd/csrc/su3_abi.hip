@@ -8,6 +8,8 @@ namespace {
 
 using namespace su3;
 
+static_assert(SU3_BWD_SCRATCH_BYTES == kScratchBytes, "su3.h and the library disagree on the scratch size");
+
 // byte sizes per site of a and c, and of the four b links, per form
 struct Form {
     int64_t a_site, c_site, b_total, b_align;
@@ -248,8 +250,11 @@ size_t su3_mult_nn_bwd_workspace_bytes(int64_t sites, int precision)
     return (size_t)bwd_workspace_doubles(sites, precision) * sizeof(double);
 }
 
-int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, double *db_f64, int64_t sites,
-                    int precision, void *ws, size_t ws_bytes, void *stream)
+// Validation shared by both adjoint entry points. ws is the caller's
+// workspace (checked for size, alignment and overlap) unless own_ws is set,
+// in which case the library's own array is used and only its size is checked.
+static int check_bwd(const void *a, const void *b, const void *dc, const void *da, const double *db_f64, int64_t sites,
+                     int precision, const void *ws, size_t ws_bytes, bool own_ws)
 {
     if (precision != SU3_F64 && precision != SU3_F32)
         return SU3_ERR_PRECISION;
@@ -262,24 +267,55 @@ int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, doub
     if (sites > 0 && (!a || !b || !dc || !da))
         return SU3_ERR_NULL;
     const size_t need = su3_mult_nn_bwd_workspace_bytes(sites, precision);
-    if (sites > 0 && (!ws || ws_bytes < need))
+    if (own_ws) {
+        if (need > kScratchBytes)
+            return SU3_ERR_WORKSPACE;
+    } else if (sites > 0 && (!ws || ws_bytes < need)) {
         return SU3_ERR_WORKSPACE;
+    }
     if (!aligned(db_f64, 8))
         return SU3_ERR_ALIGN;
     if (sites > 0 && (!aligned(a, 16) || !aligned(dc, 16) || !aligned(da, 16) || !aligned(b, f.b_align) ||
-                      !aligned(ws, 16)))
+                      (!own_ws && !aligned(ws, 16))))
         return SU3_ERR_ALIGN;
     const int64_t n = sites * f.a_site;
     if (sites > 0 && (overlap(da, n, a, n) || overlap(da, n, dc, n) || overlap(da, n, b, f.b_total) ||
                       overlap(db_f64, 576, a, n) || overlap(db_f64, 576, dc, n) || overlap(db_f64, 576, da, n) ||
-                      overlap(db_f64, 576, b, f.b_total) || overlap(ws, (int64_t)need, a, n) ||
-                      overlap(ws, (int64_t)need, dc, n) || overlap(ws, (int64_t)need, da, n) ||
-                      overlap(ws, (int64_t)need, b, f.b_total) || overlap(ws, (int64_t)need, db_f64, 576)))
+                      overlap(db_f64, 576, b, f.b_total)))
         return SU3_ERR_OVERLAP;
+    if (sites > 0 && !own_ws &&
+        (overlap(ws, (int64_t)need, a, n) || overlap(ws, (int64_t)need, dc, n) || overlap(ws, (int64_t)need, da, n) ||
+         overlap(ws, (int64_t)need, b, f.b_total) || overlap(ws, (int64_t)need, db_f64, 576)))
+        return SU3_ERR_OVERLAP;
+    return SU3_OK;
+}
+
+int su3_mult_nn_bwd(const void *a, const void *b, const void *dc, void *da, double *db_f64, int64_t sites,
+                    int precision, void *ws, size_t ws_bytes, void *stream)
+{
+    const int st = check_bwd(a, b, dc, da, db_f64, sites, precision, ws, ws_bytes, false);
+    if (st != SU3_OK)
+        return st;
     hipStream_t s = (hipStream_t)stream;
     if (sites == 0)
         return status_of(launch_bwd_zero(db_f64, s));
     return status_of(launch_bwd(a, b, dc, da, db_f64, sites, precision, (double *)ws, s));
+}
+
+int su3_mult_nn_bwd_noalloc(const void *a, const void *b, const void *dc, void *da, double *db_f64, int64_t sites,
+                            int precision, void *stream)
+{
+    const int st = check_bwd(a, b, dc, da, db_f64, sites, precision, nullptr, 0, true);
+    if (st != SU3_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (sites == 0)
+        return status_of(launch_bwd_zero(db_f64, s));
+    double *ws = nullptr;
+    const hipError_t e = bwd_scratch(&ws);
+    if (e != hipSuccess)
+        return SU3_ERR_HIP;
+    return status_of(launch_bwd(a, b, dc, da, db_f64, sites, precision, ws, s));
 }
 
 int su3_stream_copy(const void *src, void *dst, int64_t bytes, void *stream)

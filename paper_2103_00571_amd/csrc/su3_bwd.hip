@@ -98,14 +98,14 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ 
     constexpr int kStageBytes = 2 * 3 * 64 * 16;     // a and dC tiles
     constexpr int kRedBytes = 64 * 19 * 8;           // one row's 18 accumulators per lane, padded
     constexpr int kBytes = kStageBytes > kRedBytes ? kStageBytes : kRedBytes;
-    // per-wavefront scratch: tile staging in the loop, reduction after it
-    __shared__ __attribute__((aligned(16))) char scratch[kBwdWaves][kBytes];
+    // per-wavefront LDS: tile staging in the loop, reduction after it
+    __shared__ __attribute__((aligned(16))) char tilebuf[kBwdWaves][kBytes];
     __shared__ double rowsum[kBwdWaves][12 * 18];
     __shared__ S bsh[72];
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    u4 *stage = reinterpret_cast<u4 *>(scratch[wv]);
-    double *red = reinterpret_cast<double *>(scratch[wv]);
+    u4 *stage = reinterpret_cast<u4 *>(tilebuf[wv]);
+    double *red = reinterpret_cast<double *>(tilebuf[wv]);
     // this workgroup's tile group; its partial goes to slot grp
     const int64_t grp = SU3_BWD_XCD_ORDER ? xcd_order(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int64_t t0 = grp * kBwdWaves * kTiles + wv;
@@ -378,6 +378,36 @@ hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, do
 hipError_t launch_bwd_zero(double *db, hipStream_t s)
 {
     return launch_k(bwd_reduce, dim3(72), dim3(kReduceThreads), s, 0, (const double *)nullptr, db, (int64_t)0);
+}
+
+// ---- the library-owned workspace of su3_mult_nn_bwd_noalloc ---------------
+// A fixed device array (each device the library runs on holds its own copy
+// until the process ends). Its name is only a host-side handle: host code
+// uses the device address that hipGetSymbolAddress returns for the current
+// device, kept per device in scratch_ptr.
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+static std::atomic<double *> scratch_ptr[kMaxDevices];
+
+hipError_t bwd_scratch(double **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    double *p = scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p == nullptr) {
+        // racing first calls on one device get the same address
+        e = hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (p == nullptr)
+            return hipErrorInvalidSymbol;
+        scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+    *ptr = p;
+    return hipSuccess;
 }
 
 } // namespace su3

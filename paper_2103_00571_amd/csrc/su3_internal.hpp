@@ -173,5 +173,10 @@ int bwd_block_threads();
 hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, double *db, int64_t sites,
                       int precision, double *ws, hipStream_t s);
 hipError_t launch_bwd_zero(double *db, hipStream_t s);
+// Bytes of the library-owned adjoint workspace (one static device array per
+// device) and its device address on the current device, looked up on the
+// first call per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t bwd_scratch(double **ptr);
 
 } // namespace su3

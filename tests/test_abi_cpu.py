@@ -144,6 +144,28 @@ def test_bwd_validation(abi):
     assert f(A, B, D, DA, DB, -1, 0, WS, ws_need, None) == abi.SU3_ERR_SIZE
 
 
+def test_bwd_noalloc_validation(abi):
+    """The allocation-free adjoint validates like su3_mult_nn_bwd, and refuses
+    a lattice whose workspace exceeds the library's array, before any HIP call
+    (so before the array's address is even looked up)."""
+    D, DA, DB = 1 << 41, 1 << 42, 1 << 43
+    f = abi.su3_mult_nn_bwd_noalloc
+    assert abi.SU3_BWD_SCRATCH_BYTES == 64 << 20
+    for form in (0, 1):
+        big = 1
+        while abi.su3_mult_nn_bwd_workspace_bytes(big, form) <= abi.SU3_BWD_SCRATCH_BYTES:
+            big *= 2
+        assert f(A, B, D, DA, DB, big, form, None) == abi.SU3_ERR_WORKSPACE
+        assert abi.su3_mult_nn_bwd_workspace_bytes(48 ** 4, form) <= abi.SU3_BWD_SCRATCH_BYTES
+        assert f(A, B, D, DA, DB, -1, form, None) == abi.SU3_ERR_SIZE
+        assert f(A, B, D, DA, 0, 1000, form, None) == abi.SU3_ERR_NULL
+        assert f(0, B, D, DA, DB, 1000, form, None) == abi.SU3_ERR_NULL
+        assert f(A, B, D, A, DB, 1000, form, None) == abi.SU3_ERR_OVERLAP
+        assert f(A, B, D, DA, DA + 64, 1000, form, None) == abi.SU3_ERR_OVERLAP
+        assert f(A, B, D, DA + 8, DB, 1000, form, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B, D, DA, DB, 1000, 2, None) == abi.SU3_ERR_PRECISION
+
+
 def test_stream_copy_validation(abi):
     assert abi.su3_stream_copy(A, C, 0, None) == abi.SU3_OK
     assert abi.su3_stream_copy(A, C, 24, None) == abi.SU3_ERR_SIZE
