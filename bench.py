@@ -58,6 +58,9 @@ PAPER_CONTEXT = {
 }
 KERNEL_SOURCES = ["paper_2103_00571_amd/csrc/su3_fwd.hip", "paper_2103_00571_amd/csrc/su3_internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_aos_f64_L48.json")
+# Untimed warm-up, in seconds, of every leg after the headline (which runs W
+# untimed steps right after the device warm-up).
+LEG_WARM_S = 0.1
 
 
 def log(msg: str) -> None:
@@ -80,12 +83,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_launches(fn, steps: int, warmup: int, torch) -> float:
+def time_launches(fn, steps: int, warmup: int, torch, warm_seconds: float = 0.0) -> float:
     """Average milliseconds per call of fn() over `steps` back-to-back calls,
-    from HIP events on the current stream (where fn launches)."""
+    from HIP events on the current stream (where fn launches). Before timing:
+    `warmup` untimed calls, then more untimed calls until at least
+    `warm_seconds` of them have run (the GPU takes tens of milliseconds to
+    return to its steady rate after an idle stretch, such as host-side input
+    generation between two legs)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if warm_seconds > 0:
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < warm_seconds:
+            for _ in range(10):
+                fn()
+            torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
@@ -280,7 +293,7 @@ def main() -> int:
     if "shard8" in forms and sites >= 8:
         ns = sites // 8
         xs, ys = ta[:ns], torch.empty_like(ta[:ns])
-        ms = time_launches(lambda: ops.mult_nn(xs, tb64, out=ys), args.steps, args.warmup, torch)
+        ms = time_launches(lambda: ops.mult_nn(xs, tb64, out=ys), args.steps, args.warmup, torch, LEG_WARM_S)
         record("shard8", ms, BYTES_PER_SITE["f64"], ns)
         results["shard8"]["sites"] = ns
         del ys
@@ -294,18 +307,18 @@ def main() -> int:
     if "l32" in forms and sites >= n32:
         x64 = ta[:n32]
         y64 = torch.empty_like(x64)
-        ms = time_launches(lambda: ops.mult_nn(x64, tb64, out=y64), steps32, args.warmup, torch)
+        ms = time_launches(lambda: ops.mult_nn(x64, tb64, out=y64), steps32, args.warmup, torch, LEG_WARM_S)
         record("f64_L32", ms, BYTES_PER_SITE["f64"], n32)
         results["f64_L32"].update({"sites": n32, "steps": steps32})
         x32 = ops.pack(x64, ops.SU3_F32)
         y32 = torch.empty_like(x32)
-        ms = time_launches(lambda: ops.mult_nn(x32, tb32, out=y32), steps32, args.warmup, torch)
+        ms = time_launches(lambda: ops.mult_nn(x32, tb32, out=y32), steps32, args.warmup, torch, LEG_WARM_S)
         record("f32_L32", ms, BYTES_PER_SITE["f32"], n32)
         results["f32_L32"].update({"sites": n32, "steps": steps32})
         for name, x, tb, key in (("soa_L32", x64, tb64, "f64_L32"), ("soa32_L32", x32, tb32, "f32_L32")):
             sa = ops.aos_to_soa(x)
             sc = torch.empty_like(sa)
-            ms = time_launches(lambda: ops.mult_nn_soa(sa, tb, out=sc), steps32, args.warmup, torch)
+            ms = time_launches(lambda: ops.mult_nn_soa(sa, tb, out=sc), steps32, args.warmup, torch, LEG_WARM_S)
             record(name, ms, BYTES_PER_SITE["soa" if name == "soa_L32" else "soa32"], n32)
             results[name].update({"sites": n32, "steps": steps32,
                                   "vs_site_major": results[key]["ms"] / ms})
@@ -315,8 +328,8 @@ def main() -> int:
     # ---- streaming copy over the same footprint (measured bandwidth) -------
     if "copy" in forms:
         dst = torch.empty_like(ta)
-        msc = time_launches(lambda: ops.stream_copy(ta, dst), args.steps, args.warmup, torch)
-        msd = time_launches(lambda: dst.copy_(ta), max(10, args.steps // 4), 2, torch)
+        msc = time_launches(lambda: ops.stream_copy(ta, dst), args.steps, args.warmup, torch, LEG_WARM_S)
+        msd = time_launches(lambda: dst.copy_(ta), max(10, args.steps // 4), 2, torch, LEG_WARM_S)
         nb = 2 * a.nbytes
         results["copy"] = {"ms": msc, "gb_s": nb / (msc * 1e-3) / 1e9, "bytes_moved": nb,
                            "torch_copy_ms": msd, "torch_copy_gb_s": nb / (msd * 1e-3) / 1e9}
@@ -367,7 +380,7 @@ def main() -> int:
     if "soa" in forms:
         sa = ops.aos_to_soa(ta)
         sc = torch.empty_like(sa)
-        ms = time_launches(lambda: ops.mult_nn_soa(sa, tb64, out=sc), args.steps, args.warmup, torch)
+        ms = time_launches(lambda: ops.mult_nn_soa(sa, tb64, out=sc), args.steps, args.warmup, torch, LEG_WARM_S)
         record("soa", ms, BYTES_PER_SITE["soa"], sites)
         results["soa"]["vs_site_major"] = ms64 / ms
         outputs["soa"] = ops.soa_to_aos(sc)
@@ -379,7 +392,7 @@ def main() -> int:
             continue
         x = ops.pack(ta, code)
         y = ops.mult_nn(x, tb32)
-        ms = time_launches(lambda: ops.mult_nn(x, tb32, out=y), args.steps, args.warmup, torch)
+        ms = time_launches(lambda: ops.mult_nn(x, tb32, out=y), args.steps, args.warmup, torch, LEG_WARM_S)
         record(name, ms, BYTES_PER_SITE[name], sites)
         outputs[name] = y
         del x
@@ -388,14 +401,14 @@ def main() -> int:
         x = ops.pack(ta, ops.SU3_R12C_F32)
         y = ops.mult_nn(x, tb32, form=ops.SU3_R12C_F32)
         ms = time_launches(lambda: ops.mult_nn(x, tb32, out=y, form=ops.SU3_R12C_F32), args.steps, args.warmup,
-                           torch)
+                           torch, LEG_WARM_S)
         record("r12c", ms, BYTES_PER_SITE["r12c"], sites)
         outputs["r12c"] = ops.unpack(y, ops.SU3_R12C_F32)   # product with row 2 rebuilt, for the error report
         del x, y
     if "r12f64" in forms:
         x = ops.pack(ta, ops.SU3_R12_F64)
         y = ops.mult_nn(x, tb64)
-        ms = time_launches(lambda: ops.mult_nn(x, tb64, out=y), args.steps, args.warmup, torch)
+        ms = time_launches(lambda: ops.mult_nn(x, tb64, out=y), args.steps, args.warmup, torch, LEG_WARM_S)
         record("r12f64", ms, BYTES_PER_SITE["r12f64"], sites)
         outputs["r12f64"] = y
         del x
@@ -403,13 +416,13 @@ def main() -> int:
     for name, fn in (("na", ops.mult_na), ("an", ops.mult_an)):
         if name in forms:
             y = torch.empty_like(ta)
-            ms = time_launches(lambda: fn(ta, tb64, out=y), args.steps, args.warmup, torch)
+            ms = time_launches(lambda: fn(ta, tb64, out=y), args.steps, args.warmup, torch, LEG_WARM_S)
             record(name, ms, BYTES_PER_SITE[name], sites)
             del y
     if "matvec" in forms:
         tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=4)[:, 0, 0, :].copy()).to(dev)
         w = ops.mat_vec(ta, tv)
-        ms = time_launches(lambda: ops.mat_vec(ta, tv, out=w), args.steps, args.warmup, torch)
+        ms = time_launches(lambda: ops.mat_vec(ta, tv, out=w), args.steps, args.warmup, torch, LEG_WARM_S)
         record("matvec", ms, BYTES_PER_SITE["matvec"], sites)
         del tv, w
     # ---- setup kernels: layout transforms and storage-form conversions -------
@@ -422,7 +435,7 @@ def main() -> int:
         setup = {}
 
         def rec_setup(name, fn, nbytes):
-            ms = time_launches(fn, k, 3, torch)
+            ms = time_launches(fn, k, 3, torch, LEG_WARM_S)
             setup[name] = {"ms": ms, "gb_s": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes}
             log("setup %-12s %8.4f ms  %7.1f GB/s" % (name, ms, nbytes / (ms * 1e-3) / 1e9))
 
@@ -443,20 +456,20 @@ def main() -> int:
         t32 = ta.to(torch.complex64)
         sa = ops.aos_to_soa(t32)
         sc = torch.empty_like(sa)
-        record("soa32", time_launches(lambda: ops.mult_nn_soa(sa, tb32, out=sc), args.steps, args.warmup, torch),
+        record("soa32", time_launches(lambda: ops.mult_nn_soa(sa, tb32, out=sc), args.steps, args.warmup, torch, LEG_WARM_S),
                BYTES_PER_SITE["soa32"], sites)
         if "f32" in results:
             results["soa32"]["vs_site_major"] = results["f32"]["ms"] / results["soa32"]["ms"]
         del sa, sc
         y = torch.empty_like(t32)
         for name, fn in (("na32", ops.mult_na), ("an32", ops.mult_an)):
-            record(name, time_launches(lambda: fn(t32, tb32, out=y), args.steps, args.warmup, torch),
+            record(name, time_launches(lambda: fn(t32, tb32, out=y), args.steps, args.warmup, torch, LEG_WARM_S),
                    BYTES_PER_SITE[name], sites)
         del y
         tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=4)[:, 0, 0, :].copy()).to(dev)
         tv = tv.to(torch.complex64)
         w = ops.mat_vec(t32, tv)
-        record("matvec32", time_launches(lambda: ops.mat_vec(t32, tv, out=w), args.steps, args.warmup, torch),
+        record("matvec32", time_launches(lambda: ops.mat_vec(t32, tv, out=w), args.steps, args.warmup, torch, LEG_WARM_S),
                BYTES_PER_SITE["matvec32"], sites)
         del t32, tv, w
     for name in ("f32", "bf16", "r12", "r12c", "r12f64", "soa"):
@@ -484,7 +497,7 @@ def main() -> int:
                 da_, db_ = torch.empty_like(xa_), torch.empty((4, 3, 3), dtype=torch.complex128, device=dev)
                 ws_ = ops.mult_nn_bwd_workspace(bs, ops.form_of(xa_), dev)
                 ms = time_launches(lambda: ops.mult_nn_bwd(xa_, tb, xdc_, da=da_, db=db_, ws=ws_), args.steps,
-                                   args.warmup, torch)
+                                   args.warmup, torch, LEG_WARM_S)
                 nb = BWD_BYTES_PER_SITE[name[4:]] * bs
                 results[name] = {"ms": ms, "sites_per_s": bs / (ms * 1e-3), "gb_s": nb / (ms * 1e-3) / 1e9,
                                  "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "L": args.bwd_L,

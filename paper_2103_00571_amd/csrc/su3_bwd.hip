@@ -5,14 +5,18 @@
 //   dB[j]    = sum_s A[s][j]^H dC[s][j]     (a sum over every site)
 // The paper has no adjoint; these are the two contractions of its product.
 //
-// Stage 1 (bwd_tiles). A thread owns one unit of output rows (FP64: one row,
-// FP32: two rows), as in the forward kernel, and a wavefront streams tiles of
-// 64 units: whole 1 KiB global runs of dC and A, transposed to one unit per
-// lane through LDS. Per row k of link j it writes row k of dA and adds
-// conj(A(k, m)) dC(k, l) (m, l = 0..2) to FP64 accumulators. A wavefront
-// takes kTiles tiles spaced 3 tiles apart, so a lane keeps the same row
-// position (and link) on every tile and its accumulators stay valid; a
-// workgroup of 3 wavefronts covers 3*kTiles consecutive tiles.
+// Stage 1 (bwd_tiles). A lane owns one row (3 complex) of a link at a time,
+// 48 B in FP64 and 24 B in FP32, and a wavefront streams steps of 3 chunks
+// per lane of dC and A (whole 1 KiB global runs; one 64-row tile in FP64,
+// two in FP32), transposed to one row per lane through LDS. Per row k of
+// link j it writes row k of dA and adds conj(A(k, m)) dC(k, l) (m, l = 0..2)
+// to 18 FP64 accumulators. The tiles of a wavefront are spaced a multiple of
+// 3 tiles (192 rows, a multiple of the 12 rows of a site) apart, so a lane
+// keeps one row position, hence one link and one accumulator set, on every
+// tile. A workgroup of 3 wavefronts takes kSteps steps each; in FP64 the
+// workgroups are taken in batches of 256 and step k of every workgroup of a
+// batch lies in one contiguous block (phase striping), which keeps the
+// workgroups that run together on one contiguous front.
 // At the end the lanes' accumulators are summed in a fixed order: per row
 // position within the wavefront (lanes in increasing order), then per link
 // over the workgroup's wavefronts and the link's three rows. Each workgroup
@@ -23,11 +27,13 @@
 // 8-byte store costs a whole sector of HBM writes).
 // Stage 2 reduces the partials of each of the 72 real components in two
 // fixed-order levels: bwd_chunk_sums adds runs of kChunk consecutive partials
-// of a quad's 4 components (8 per thread, then a binary tree per component),
-// bwd_reduce adds the run sums, stored component-major (one wavefront per
-// component: a strided loop, then a binary tree across the lanes). Both
-// levels keep every load of a thread in flight at once, so stage 2 costs a
-// few microseconds at any lattice size.
+// of a quad's 4 components (8 per thread, then a shuffle tree per wavefront
+// and the wavefronts in order), bwd_reduce adds the run sums, stored
+// component-major (one wavefront per component: a strided loop, then a
+// shuffle tree). With a single run per component the first level writes dB
+// itself and the second is not launched. Both levels keep every load of a
+// thread in flight at once, so stage 2 costs a few microseconds at any
+// lattice size.
 // The number of workgroups of every stage depends only on the number of sites
 // and the form, so the rounding sequence, and every bit of dB, is the same on
 // every run and every device. No atomics.
@@ -37,16 +43,17 @@ namespace su3 {
 
 constexpr int kBwdWaves = 3;                 // wavefronts per workgroup
 constexpr int kBwdThreads = 64 * kBwdWaves;
-// Tiles per wavefront and resident wavefronts per CU for stage 1 (0: as many
-// as fit), measured at L=32 over 1, 2, 3, 4, 6, 8 and 16 tiles and 3, 6, 9 or
-// 12 wavefronts.
-// More tiles per wavefront amortise the closing reduction; fewer shorten the
-// drain at the end of the grid.
+// Steps per wavefront and resident wavefronts per CU for stage 1 (0: as many
+// as fit), from sweeps at L=32 over 1 to 128 steps, caps of 6, 9 and 12
+// wavefronts and batches of 32 to 3072 workgroups (or none). More steps
+// amortise the closing reduction and cut the partials stage 2 reads; fewer
+// shorten the drain at the end of the grid and keep the workgroups from
+// drifting apart in memory.
 #ifndef SU3_BWD_TILES_F64
 #define SU3_BWD_TILES_F64 4
 #endif
 #ifndef SU3_BWD_TILES_F32
-#define SU3_BWD_TILES_F32 4
+#define SU3_BWD_TILES_F32 2
 #endif
 #ifndef SU3_BWD_WAVES_F64
 #define SU3_BWD_WAVES_F64 9
@@ -59,21 +66,39 @@ constexpr int kBwdThreads = 64 * kBwdWaves;
 #ifndef SU3_BWD_XCD_ORDER
 #define SU3_BWD_XCD_ORDER 0
 #endif
+// Phase striping of stage 1 (0: off): the workgroups are taken in batches
+// of kBatch, and step k of every workgroup of a batch lies in one
+// contiguous block of the batch's tiles, so the workgroups that run at the
+// same time stream one contiguous front instead of each its own run.
+#ifndef SU3_BWD_BATCH_F64
+#define SU3_BWD_BATCH_F64 256
+#endif
+#ifndef SU3_BWD_BATCH_F32
+#define SU3_BWD_BATCH_F32 0
+#endif
 
-// FP64: unit = one row (3 complex, 48 B); 12 units per site.
+// The two forms: kSub 64-row tiles per step (3 chunks per lane of each
+// array), kSteps steps per wavefront, phase-striping batch kBatch.
 struct BwdF64 {
     typedef double S;
-    static constexpr int kRows = 1, kUnitsPerSite = 12, kTiles = SU3_BWD_TILES_F64;
+    static constexpr int kSub = 1, kSteps = SU3_BWD_TILES_F64, kBatch = SU3_BWD_BATCH_F64;
 };
-// FP32: unit = two rows (6 complex float, 48 B); 6 units per site.
 struct BwdF32 {
     typedef float S;
-    static constexpr int kRows = 2, kUnitsPerSite = 6, kTiles = SU3_BWD_TILES_F32;
+    static constexpr int kSub = 2, kSteps = SU3_BWD_TILES_F32, kBatch = SU3_BWD_BATCH_F32;
 };
+constexpr int kRowsPerSite = 12;
 
-// Stage 2, first level: partials per workgroup.
-constexpr int kChunkLoads = 8;
-constexpr int64_t kChunk = (int64_t)kBlock * kChunkLoads;
+// Stage 2, first level: threads per workgroup and partials per thread.
+#ifndef SU3_BWD_CHUNK_THREADS
+#define SU3_BWD_CHUNK_THREADS 256
+#endif
+#ifndef SU3_BWD_CHUNK_LOADS
+#define SU3_BWD_CHUNK_LOADS 8
+#endif
+constexpr int kChunkThreads = SU3_BWD_CHUNK_THREADS;
+constexpr int kChunkLoads = SU3_BWD_CHUNK_LOADS;
+constexpr int64_t kChunk = (int64_t)kChunkThreads * kChunkLoads;
 
 // Order LDS traffic between the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync_bwd()
@@ -83,203 +108,248 @@ __device__ __forceinline__ void wave_sync_bwd()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row `lane` of sub-tile q of a staged step, as 6 interleaved re/im values.
+__device__ __forceinline__ void row_from_stage(const u4 *st, int q, int lane, double (&v)[6])
+{
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const d2 w = __builtin_bit_cast(d2, st[192 * q + 3 * lane + e]);
+        v[2 * e] = w.x;
+        v[2 * e + 1] = w.y;
+    }
+}
+__device__ __forceinline__ void row_from_stage(const u4 *st, int q, int lane, float (&v)[6])
+{
+    const f2 *p = reinterpret_cast<const f2 *>(st) + 192 * q + 3 * lane;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const f2 w = p[e];
+        v[2 * e] = w.x;
+        v[2 * e + 1] = w.y;
+    }
+}
+__device__ __forceinline__ void row_to_stage(u4 *st, int q, int lane, const double (&v)[6])
+{
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const d2 w = {v[2 * e], v[2 * e + 1]};
+        st[192 * q + 3 * lane + e] = __builtin_bit_cast(u4, w);
+    }
+}
+__device__ __forceinline__ void row_to_stage(u4 *st, int q, int lane, const float (&v)[6])
+{
+    f2 *p = reinterpret_cast<f2 *>(st) + 192 * q + 3 * lane;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const f2 w = {v[2 * e], v[2 * e + 1]};
+        p[e] = w;
+    }
+}
+
 template <class F>
 __global__ __launch_bounds__(kBwdThreads) void bwd_tiles(const u4 *__restrict__ a, const typename F::S *__restrict__ b,
                                                          const u4 *__restrict__ dc, u4 *__restrict__ da,
-                                                         double *__restrict__ ws, int64_t units, int64_t groups)
+                                                         double *__restrict__ ws, int64_t rows, int64_t groups)
 {
     typedef typename F::S S;
-    typedef S SV __attribute__((ext_vector_type(16 / sizeof(S))));
-    constexpr int PV = 16 / sizeof(S);        // scalars per 16-byte chunk
-    constexpr int R = F::kRows;
-    constexpr int NV = 18 * R;                // accumulator doubles per lane
-    constexpr int P = F::kUnitsPerSite;
-    constexpr int kTiles = F::kTiles;
-    constexpr int kStageBytes = 2 * 3 * 64 * 16;     // a and dC tiles
-    constexpr int kRedBytes = 64 * 19 * 8;           // one row's 18 accumulators per lane, padded
+    constexpr int kSub = F::kSub;                     // 64-row tiles per step
+    constexpr int kSteps = F::kSteps;
+    constexpr int CT = 64 * 6 * (int)sizeof(S) / 16;  // chunks per 64-row tile: 192 or 96
+    constexpr int kStageBytes = 2 * 3 * 64 * 16;      // a and dC, 3 chunks per lane each
+    constexpr int kRedBytes = 64 * 19 * 8;            // 18 accumulators per lane, padded
     constexpr int kBytes = kStageBytes > kRedBytes ? kStageBytes : kRedBytes;
-    // per-wavefront LDS: tile staging in the loop, reduction after it
+    // per-wavefront LDS: step staging in the loop, reduction after it
     __shared__ __attribute__((aligned(16))) char tilebuf[kBwdWaves][kBytes];
-    __shared__ double rowsum[kBwdWaves][12 * 18];
+    __shared__ double rowsum[kBwdWaves][kRowsPerSite * 18];
     __shared__ S bsh[72];
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    u4 *stage = reinterpret_cast<u4 *>(tilebuf[wv]);
+    u4 *stg = reinterpret_cast<u4 *>(tilebuf[wv]);    // dC at [0, 192), A at [192, 384)
     double *red = reinterpret_cast<double *>(tilebuf[wv]);
     // this workgroup's tile group; its partial goes to slot grp
     const int64_t grp = SU3_BWD_XCD_ORDER ? xcd_order(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t t0 = grp * kBwdWaves * kTiles + wv;
-    const int64_t nchunks = units * 3;
+    // the wavefront's first 64-row tile t0; it takes t0 + D i for
+    // i < kSub * kSteps (D a multiple of 3)
+    constexpr int kPer = kBwdWaves * kSub * kSteps;   // tiles per workgroup
+    int64_t t0, D;
+    if constexpr (F::kBatch > 0) {
+        constexpr int kB = F::kBatch;
+        const int64_t bt = grp / kB, lam = grp - bt * kB;
+        const int64_t nb = groups - bt * kB < kB ? groups - bt * kB : (int64_t)kB;
+        t0 = bt * kPer * kB + kBwdWaves * lam + wv;
+        D = kBwdWaves * nb;
+    } else {
+        t0 = grp * kPer + wv;
+        D = kBwdWaves;
+    }
+    const int64_t nchunks = rows * 6 * (int64_t)sizeof(S) / 16;
 
     if (threadIdx.x < 72)
         bsh[threadIdx.x] = b[threadIdx.x];
     __syncthreads();
 
-    const int pos = (int)((t0 * 64 + lane) % P);   // unit position in the site
-    // row h of the unit is site row R*pos + h, which belongs to link (R*pos+h)/3
-    S br[R][9], bi[R][9];
+    const int pos = (int)((t0 * 64 + lane) % kRowsPerSite);   // row position in the site
+    const int j = pos / 3;                                     // its link
+    S br[9], bi[9];
 #pragma unroll
-    for (int h = 0; h < R; ++h) {
-        const int j = (R * pos + h) / 3;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            br[h][q] = bsh[2 * (9 * j + q)];
-            bi[h][q] = bsh[2 * (9 * j + q) + 1];
-        }
+    for (int q = 0; q < 9; ++q) {
+        br[q] = bsh[2 * (9 * j + q)];
+        bi[q] = bsh[2 * (9 * j + q) + 1];
     }
-    double acc[NV];
+    double acc[18];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < 18; ++v)
         acc[v] = 0.0;
 
-    // Tile loads: chunk indices past the end re-read the last chunk (in
-    // bounds; those lanes store nothing and add nothing). The loads of the
-    // next tile are issued as soon as the current tile sits in LDS, so they
-    // are in flight while the current tile is computed and stored.
+    // Global chunk of step-chunk c (c = 64 i + lane, i < 3) of the step that
+    // starts at tile ts: sub-tile c / CT, chunk c mod CT of it.
+    auto gchunk = [&](int64_t ts, int i) -> int64_t {
+        const int c = 64 * i + lane, q = c / CT;
+        return (ts + D * q) * CT + (c - q * CT);
+    };
+    // Step loads: chunks past the end re-read the last chunk (in bounds;
+    // those rows store nothing and add nothing). The loads of the next step
+    // are issued as soon as the current step sits in LDS, so they are in
+    // flight while the current step is computed and stored.
     u4 va[3], vg[3];
-    auto load_tile = [&](int64_t t) {
+    auto load_step = [&](int64_t ts) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const int64_t g = t * 64 * 3 + lane + 64 * i;
+            const int64_t g = gchunk(ts, i);
             const int64_t gc = g < nchunks ? g : nchunks - 1;
             vg[i] = ld_stream(dc + gc);
             va[i] = ld_stream(a + gc);
         }
     };
-    if (t0 * 64 < units)
-        load_tile(t0);
-    for (int k = 0; k < kTiles; ++k) {
-        const int64_t t = t0 + (int64_t)kBwdWaves * k;
-        if (t * 64 >= units)
-            break;                                   // wave-uniform
-        const bool whole = (t + 1) * 64 <= units;
-        const int64_t g0 = t * 64 * 3 + lane;
+    if (t0 * 64 < rows)
+        load_step(t0);
+    for (int k = 0; k < kSteps; ++k) {
+        const int64_t ts = t0 + D * kSub * k;   // the step's first tile
+        if (ts * 64 >= rows)
+            break;                              // wave-uniform
+        // every row of the step's last tile is in the lattice
+        const bool whole = (ts + D * (kSub - 1) + 1) * 64 <= rows;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            stage[64 * i + lane] = vg[i];
-            stage[192 + 64 * i + lane] = va[i];
+            stg[64 * i + lane] = vg[i];
+            stg[192 + 64 * i + lane] = va[i];
         }
         wave_sync_bwd();
-        if (k + 1 < kTiles && (t + kBwdWaves) * 64 < units)
-            load_tile(t + kBwdWaves);
-        S g[6 * R], x[6 * R];   // interleaved re/im of the unit's R rows
+        if (k + 1 < kSteps && (ts + D * kSub) * 64 < rows)
+            load_step(ts + D * kSub);
+        S o[kSub][6];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const SV wg = __builtin_bit_cast(SV, stage[3 * lane + i]);
-            const SV wa = __builtin_bit_cast(SV, stage[192 + 3 * lane + i]);
-#pragma unroll
-            for (int e = 0; e < PV; ++e) {
-                g[PV * i + e] = wg[e];
-                x[PV * i + e] = wa[e];
-            }
-        }
-        // dA(k, m) = sum_l dC(k, l) conj(B(m, l)), per row h of the unit
-        S o[6 * R];
-#pragma unroll
-        for (int h = 0; h < R; ++h)
+        for (int q = 0; q < kSub; ++q) {
+            S g[6], x[6];     // interleaved re/im of dC and A row `lane` of sub-tile q
+            row_from_stage(stg, q, lane, g);
+            row_from_stage(stg + 192, q, lane, x);
+            // dA(k, m) = sum_l dC(k, l) conj(B(m, l))
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 S re = 0, im = 0;
 #pragma unroll
                 for (int l = 0; l < 3; ++l)
-                    cmac(re, im, g[6 * h + 2 * l], g[6 * h + 2 * l + 1], br[h][3 * m + l], -bi[h][3 * m + l]);
-                o[6 * h + 2 * m] = re;
-                o[6 * h + 2 * m + 1] = im;
+                    cmac(re, im, g[2 * l], g[2 * l + 1], br[3 * m + l], -bi[3 * m + l]);
+                o[q][2 * m] = re;
+                o[q][2 * m + 1] = im;
             }
-        // dB(m, l) += conj(A(k, m)) dC(k, l), in FP64; lanes past the end of a
-        // ragged last tile hold re-read data and add nothing
-        const bool live = whole || t * 64 + lane < units;
+            // dB(m, l) += conj(A(k, m)) dC(k, l), in FP64; rows past the end
+            // of the lattice hold re-read data and add nothing
+            const bool live = whole || (ts + D * q) * 64 + lane < rows;
 #pragma unroll
-        for (int h = 0; h < 6 * R; ++h)
-            x[h] = live ? x[h] : S(0);
-#pragma unroll
-        for (int h = 0; h < R; ++h)
+            for (int h = 0; h < 6; ++h)
+                x[h] = live ? x[h] : S(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m)
 #pragma unroll
                 for (int l = 0; l < 3; ++l)
-                    cmac(acc[18 * h + 6 * m + 2 * l], acc[18 * h + 6 * m + 2 * l + 1], (double)x[6 * h + 2 * m],
-                         -(double)x[6 * h + 2 * m + 1], (double)g[6 * h + 2 * l], (double)g[6 * h + 2 * l + 1]);
-        wave_sync_bwd();
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            SV w;
-#pragma unroll
-            for (int e = 0; e < PV; ++e)
-                w[e] = o[PV * i + e];
-            stage[3 * lane + i] = __builtin_bit_cast(u4, w);
+                    cmac(acc[6 * m + 2 * l], acc[6 * m + 2 * l + 1], (double)x[2 * m], -(double)x[2 * m + 1],
+                         (double)g[2 * l], (double)g[2 * l + 1]);
         }
         wave_sync_bwd();
-        store_runs<3>(da, stage, g0, lane, whole, nchunks);
+#pragma unroll
+        for (int q = 0; q < kSub; ++q)
+            row_to_stage(stg, q, lane, o[q]);
+        wave_sync_bwd();
+        // store the dA step as 3 whole-wavefront runs, guarded past the end
+        u4 w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            w[i] = stg[64 * i + lane];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int64_t g = gchunk(ts, i);
+            if (whole || g < nchunks)
+                st_stream(da + g, w[i]);
+        }
         wave_sync_bwd();
     }
 
     // ---- fixed-order reduction --------------------------------------------
-    // One pass per row h of the unit: the lanes' 18 accumulators of row h go
-    // to LDS (row stride 19 doubles), then the row sums of the site rows
-    // r = R*w + h (w = unit position 0..P-1) are formed: output 18*r + e adds
-    // the lanes at position w, (w - base) mod P and every P-th lane after
-    // it, in increasing order. Every load of a lane is issued before the
-    // first add (fixed trip counts; a lane index past 63 reads lane 63 and
-    // adds an exact zero instead).
-    const int base = (int)((t0 * 64) % P);
-    constexpr int kLanesPerPos = (64 + P - 1) / P;    // 6 (FP64) or 11 (FP32)
-    constexpr int kPassOut = P * 18;                  // outputs per pass: 216 / R
+    // The lanes' 18 accumulators go to LDS (row stride 19 doubles); then the
+    // sums of the 12 row positions r are formed: output 18*r + e adds the
+    // lanes at position r, (r - base) mod 12 and every 12th lane after it,
+    // in increasing order. Every load of a lane is issued before the first
+    // add (fixed trip counts; a lane index past 63 reads lane 63 and adds an
+    // exact zero instead).
+    const int base = (int)((t0 * 64) % kRowsPerSite);
+    constexpr int kLanesPerPos = (64 + kRowsPerSite - 1) / kRowsPerSite;   // 6
+    constexpr int kOut = kRowsPerSite * 18;                                 // 216
 #pragma unroll
-    for (int h = 0; h < R; ++h) {
+    for (int v = 0; v < 18; ++v)
+        red[lane * 19 + v] = acc[v];
+    wave_sync_bwd();
 #pragma unroll
-        for (int v = 0; v < 18; ++v)
-            red[lane * 19 + v] = acc[18 * h + v];
-        wave_sync_bwd();
+    for (int it = 0; it < (kOut + 63) / 64; ++it) {
+        const int o3 = lane + 64 * it;
+        if (o3 < kOut) {
+            const int r = o3 / 18, e = o3 % 18;
+            const int l0 = ((r - base) % kRowsPerSite + kRowsPerSite) % kRowsPerSite;
+            double x[kLanesPerPos];
 #pragma unroll
-        for (int it = 0; it < (kPassOut + 63) / 64; ++it) {
-            const int o3 = lane + 64 * it;
-            if (o3 < kPassOut) {
-                const int w = o3 / 18, e = o3 % 18;
-                const int l0 = ((w - base) % P + P) % P;
-                double x[kLanesPerPos];
-#pragma unroll
-                for (int i = 0; i < kLanesPerPos; ++i) {
-                    const int l = l0 + P * i;
-                    const double y = red[(l < 64 ? l : 63) * 19 + e];
-                    x[i] = l < 64 ? y : 0.0;
-                }
-                double sum = x[0];
-#pragma unroll
-                for (int i = 1; i < kLanesPerPos; ++i)
-                    sum += x[i];
-                rowsum[wv][18 * (R * w + h) + e] = sum;
+            for (int i = 0; i < kLanesPerPos; ++i) {
+                const int l = l0 + kRowsPerSite * i;
+                const double y = red[(l < 64 ? l : 63) * 19 + e];
+                x[i] = l < 64 ? y : 0.0;
             }
+            double sum = x[0];
+#pragma unroll
+            for (int i = 1; i < kLanesPerPos; ++i)
+                sum += x[i];
+            rowsum[wv][o3] = sum;
         }
-        wave_sync_bwd();
     }
     __syncthreads();
     // workgroup partial of component q = 18*j + e: wavefronts in order, then
     // the link's three rows in order
     if (threadIdx.x < 72) {
-        const int j = threadIdx.x / 18, e = threadIdx.x % 18;
+        const int jj = threadIdx.x / 18, e = threadIdx.x % 18;
         double sum = 0.0;
         for (int w2 = 0; w2 < kBwdWaves; ++w2)
-            for (int r = 3 * j; r < 3 * j + 3; ++r)
+            for (int r = 3 * jj; r < 3 * jj + 3; ++r)
                 sum += rowsum[w2][18 * r + e];
         ws[4 * ((int64_t)(threadIdx.x >> 2) * groups + grp) + (threadIdx.x & 3)] = sum;
     }
 }
 
 // grid = (chunks, 18): workgroup (c, u) adds partials c*kChunk .. c*kChunk +
-// kChunk - 1 of the 4 components of quad u (thread t takes t, t + kBlock,
-// ... in order, then a tree per component) and writes run sums
-// ws2[q * chunks + c] for q = 4u .. 4u+3.
-__global__ __launch_bounds__(kBlock) void bwd_chunk_sums(const double *__restrict__ ws, double *__restrict__ ws2,
-                                                         int64_t groups, int64_t chunks)
+// kChunk - 1 of the 4 components of quad u and writes run sums
+// ws2[q * chunks + c] for q = 4u .. 4u+3. Thread t adds partials t,
+// t + kChunkThreads, ... in order; then, per component, a binary tree across
+// the lanes of each wavefront pairs lane t with t + w for w = 32, 16, ..., 1,
+// and the wavefront sums are added in wavefront order.
+__global__ __launch_bounds__(kChunkThreads) void bwd_chunk_sums(const double *__restrict__ ws,
+                                                                double *__restrict__ ws2, int64_t groups,
+                                                                int64_t chunks)
 {
-    __shared__ double red[4][kBlock];
+    constexpr int kW = kChunkThreads / 64;
+    __shared__ double red[4][kW];
     const int64_t c = blockIdx.x;
     const d2 *src = reinterpret_cast<const d2 *>(ws + 4 * (int64_t)blockIdx.y * groups);
     d2 v[kChunkLoads][2];
 #pragma unroll
     for (int i = 0; i < kChunkLoads; ++i) {
-        const int64_t g = c * kChunk + (int64_t)kBlock * i + threadIdx.x;
+        const int64_t g = c * kChunk + (int64_t)kChunkThreads * i + threadIdx.x;
         const d2 z = {0.0, 0.0};
         v[i][0] = g < groups ? src[2 * g] : z;
         v[i][1] = g < groups ? src[2 * g + 1] : z;
@@ -293,19 +363,33 @@ __global__ __launch_bounds__(kBlock) void bwd_chunk_sums(const double *__restric
         sum[3] += v[i][1].y;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        red[e][threadIdx.x] = sum[e];
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+    for (int w = 32; w > 0; w >>= 1)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            sum[e] += __shfl_down(sum[e], w, 64);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (kW == 1) {
+        // after the tree lane 0 holds the four sums
+        if (lane == 0) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                red[e][threadIdx.x] += red[e][threadIdx.x + w];
+                ws2[(int64_t)(4 * blockIdx.y + e) * chunks + c] = sum[e];
         }
-        __syncthreads();
+        return;
     }
-    if (threadIdx.x < 4)
-        ws2[(int64_t)(4 * blockIdx.y + threadIdx.x) * chunks + c] = red[threadIdx.x][0];
+    if (lane == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            red[e][wv] = sum[e];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = red[threadIdx.x][0];
+#pragma unroll
+        for (int w2 = 1; w2 < kW; ++w2)
+            t += red[threadIdx.x][w2];
+        ws2[(int64_t)(4 * blockIdx.y + threadIdx.x) * chunks + c] = t;
+    }
 }
 
 // grid = 72 workgroups of one wavefront, one per real component of dB; the
@@ -330,9 +414,9 @@ constexpr int kReduceThreads = 64;
 // Workgroups of stage 1 for `sites` (a function of the size and form only).
 int64_t bwd_groups(int64_t sites, int precision)
 {
-    const int64_t units = sites * (precision == 0 ? BwdF64::kUnitsPerSite : BwdF32::kUnitsPerSite);
-    const int64_t tiles = (units + 63) / 64;
-    const int64_t per = (int64_t)kBwdWaves * (precision == 0 ? BwdF64::kTiles : BwdF32::kTiles);
+    const int64_t tiles = (sites * kRowsPerSite + 63) / 64;
+    const int64_t per = (int64_t)kBwdWaves * (precision == 0 ? BwdF64::kSub * BwdF64::kSteps
+                                                              : BwdF32::kSub * BwdF32::kSteps);
     return (tiles + per - 1) / per;
 }
 
@@ -357,17 +441,22 @@ hipError_t launch_bwd(const void *a, const void *b, const void *dc, void *da, do
         const size_t pad =
             occupancy_pad(reinterpret_cast<const void *>(bwd_tiles<BwdF64>), SU3_BWD_WAVES_F64, kBwdThreads, pad64);
         e = launch_k(bwd_tiles<BwdF64>, dim3((unsigned)groups), dim3(kBwdThreads), s, pad, (const u4 *)a,
-                     (const double *)b, (const u4 *)dc, (u4 *)da, ws, sites * BwdF64::kUnitsPerSite, groups);
+                     (const double *)b, (const u4 *)dc, (u4 *)da, ws, sites * kRowsPerSite, groups);
     } else {
         const size_t pad =
             occupancy_pad(reinterpret_cast<const void *>(bwd_tiles<BwdF32>), SU3_BWD_WAVES_F32, kBwdThreads, pad32);
         e = launch_k(bwd_tiles<BwdF32>, dim3((unsigned)groups), dim3(kBwdThreads), s, pad, (const u4 *)a,
-                     (const float *)b, (const u4 *)dc, (u4 *)da, ws, sites * BwdF32::kUnitsPerSite, groups);
+                     (const float *)b, (const u4 *)dc, (u4 *)da, ws, sites * kRowsPerSite, groups);
     }
     if (e != hipSuccess)
         return e;
-    e = launch_k(bwd_chunk_sums, dim3((unsigned)chunks, 18), dim3(kBlock), s, 0, (const double *)ws, ws2, groups,
-                 chunks);
+    // With a single run per component (groups <= kChunk) the run sums are dB
+    // itself, component-major: the first level writes them to db directly.
+    if (chunks == 1)
+        return launch_k(bwd_chunk_sums, dim3(1, 18), dim3(kChunkThreads), s, 0, (const double *)ws, db, groups,
+                        (int64_t)1);
+    e = launch_k(bwd_chunk_sums, dim3((unsigned)chunks, 18), dim3(kChunkThreads), s, 0, (const double *)ws, ws2,
+                 groups, chunks);
     if (e != hipSuccess)
         return e;
     return launch_k(bwd_reduce, dim3(72), dim3(kReduceThreads), s, 0, (const double *)ws2, db, chunks);
