@@ -126,9 +126,10 @@ int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites, int pr
     int st = check_lattice(a, b, c, sites, precision, f);
     if (st != SU3_OK || sites == 0)
         return st;
-    if (!grid_fits(fwd_soa_grid(sites), soa_block_threads()))
+    const int es = precision == SU3_F64 ? 16 : 8;
+    if (!grid_fits(fwd_soa_grid(sites, es), soa_block_threads()))
         return SU3_ERR_SIZE;
-    return status_of(launch_fwd_soa(a, b, c, sites, precision == SU3_F64 ? 16 : 8, (hipStream_t)stream));
+    return status_of(launch_fwd_soa(a, b, c, sites, es, (hipStream_t)stream));
 }
 
 int su3_mult_na(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)

@@ -14,7 +14,8 @@
 //    uniform over a workgroup, so b[j] sits in scalar registers (fwd_soa).
 //  * The grid covers the lattice once: each wavefront streams one tile and
 //    exits. In the site-major kernels each XCD takes one contiguous eighth of
-//    the tiles (xcd_tile); the SoA kernel keeps tile = workgroup index.
+//    the tiles (xcd_tile); the SoA kernel picks its order from the plane
+//    stride (soa_xcd).
 //  * a and c are streamed with nontemporal 16-byte loads and stores.
 //  * 64-bit offsets throughout (a FP64 L=48 lattice is 3.06e9 bytes).
 #include "su3_internal.hpp"
@@ -467,17 +468,24 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 }
 
 // ---------------------------------------------------------------- SoA
-// Thread per (site, output row): blockIdx.y = 3j + k selects the row, so the
-// link j and the b[j] entries are uniform over the workgroup (scalar
-// registers). A wavefront reads planes (j, k, 0..2) and writes planes
-// (j, k, 0..2), each access one contiguous 1 KiB (FP64) or 512 B (FP32) run.
+// Thread per (site, output row): the row 3j + k is uniform over a workgroup,
+// so the link j and the b[j] entries sit in scalar registers. A wavefront
+// reads planes (j, k, 0..2) and writes planes (j, k, 0..2), each access one
+// contiguous 1 KiB (FP64) or 512 B (FP32) run. The grid is one dimension of
+// 12 rows x nbp workgroups; workgroup `local` of a row takes site block
+// local (tile = workgroup index) or, with xcd set, xcd_order(local, nbp),
+// which gives each XCD one contiguous eighth of the row's site blocks (nbp
+// is then the row's block count rounded up to a multiple of 8, so that
+// `local` mod 8 is the XCD; the extra workgroups find no sites and exit).
 template <typename V, typename S>
 __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, const S *__restrict__ b,
-                                                  V *__restrict__ c, int64_t n)
+                                                  V *__restrict__ c, int64_t n, int64_t nbp, int xcd)
 {
-    const int row = blockIdx.y;          // 3j + k
+    const int row = (int)(blockIdx.x / nbp);     // 3j + k
+    const int64_t local = (int64_t)blockIdx.x - (int64_t)row * nbp;
+    const int64_t xb = xcd ? xcd_order(local, nbp) : local;
     const int j = row / 3;
-    const int64_t s = (int64_t)blockIdx.x * kSoaBlock + threadIdx.x;
+    const int64_t s = xb * kSoaBlock + threadIdx.x;
     if (s >= n)
         return;
     S br[9], bi[9];
@@ -501,6 +509,30 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
         V o = {re, im};
         st_stream(cp + l * n, o);
     }
+}
+
+// Tile order of the SoA product. The three input planes of a row are read at
+// the same site offsets, plane stride n * elem_bytes apart. When that stride
+// is close to a multiple of 4 MiB (within 128 KiB), the planes of the one
+// window that tile = workgroup index streams collide in HBM and FP64 runs at
+// 0.89-0.93 of the site-major rate (sizes 2^20 +- 64, 2^20 + 4096, 3 * 2^19,
+// 2^21, 2^22); the XCD-contiguous order spreads the row over eight windows
+// and runs at 0.94-0.97 there, but at other strides it is 1-7% slower than
+// tile = workgroup index (sizes 24^4, 36^4, 40^4, 48^4, 56^4, 17 * 2^16). FP32
+// keeps tile = workgroup index at every stride (the XCD order measured equal
+// or slower).
+static bool soa_xcd(int64_t sites, int elem_bytes)
+{
+    if (elem_bytes != 16)
+        return false;
+    const int64_t m = (sites * 16) % ((int64_t)4 << 20);
+    return m < ((int64_t)128 << 10) || m > ((int64_t)4 << 20) - ((int64_t)128 << 10);
+}
+
+static int64_t soa_blocks_per_row(int64_t sites, int elem_bytes)
+{
+    const int64_t nb = (sites + kSoaBlock - 1) / kSoaBlock;
+    return soa_xcd(sites, elem_bytes) ? (nb + kXcds - 1) / kXcds * kXcds : nb;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -565,7 +597,7 @@ int64_t fwd_an_grid(int precision, int64_t sites)
     return precision == 0 ? aos_grid<FormAnF64>(sites) : aos_grid<FormAnF32>(sites);
 }
 
-int64_t fwd_soa_grid(int64_t sites) { return (sites + kSoaBlock - 1) / kSoaBlock; }
+int64_t fwd_soa_grid(int64_t sites, int elem_bytes) { return 12 * soa_blocks_per_row(sites, elem_bytes); }
 int soa_block_threads() { return kSoaBlock; }
 
 template <class F, bool kConjB = false>
@@ -607,16 +639,19 @@ hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, i
 hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s)
 {
     static std::atomic<int> pad64[kMaxDevices], pad32[kMaxDevices];
-    const dim3 grid((unsigned)fwd_soa_grid(sites), 12);
+    const int64_t nbp = soa_blocks_per_row(sites, elem_bytes);
+    const int xcd = soa_xcd(sites, elem_bytes) ? 1 : 0;
+    const dim3 grid((unsigned)(12 * nbp));
     if (elem_bytes == 16) {
         const size_t pad =
             occupancy_pad(reinterpret_cast<const void *>(fwd_soa<d2, double>), SU3_WAVES_SOA_F64, kSoaBlock, pad64);
         return launch_k(fwd_soa<d2, double>, grid, dim3(kSoaBlock), s, pad, (const d2 *)a, (const double *)b, (d2 *)c,
-                        sites);
+                        sites, nbp, xcd);
     }
     const size_t pad =
         occupancy_pad(reinterpret_cast<const void *>(fwd_soa<f2, float>), SU3_WAVES_SOA_F32, kSoaBlock, pad32);
-    return launch_k(fwd_soa<f2, float>, grid, dim3(kSoaBlock), s, pad, (const f2 *)a, (const float *)b, (f2 *)c, sites);
+    return launch_k(fwd_soa<f2, float>, grid, dim3(kSoaBlock), s, pad, (const f2 *)a, (const float *)b, (f2 *)c, sites,
+                    nbp, xcd);
 }
 
 } // namespace su3

@@ -141,7 +141,7 @@ size_t occupancy_pad_for(const void *kernel, int waves, int block, int dev);
 // ---- launchers (each returns hipSuccess or the launch error) --------------
 // Forward products. The grid covers the lattice once; *_grid report it.
 int64_t fwd_aos_grid(int precision, int64_t sites);
-int64_t fwd_soa_grid(int64_t sites);
+int64_t fwd_soa_grid(int64_t sites, int elem_bytes);
 int soa_block_threads();
 hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s);
 // The a b^H and a^H b products (FP64 = 0, FP32 = 1).

@@ -240,3 +240,28 @@ def test_every_grid_residue_exact_large(ops):
         assert same(ops.mult_nn(ops.pack(a, ops.SU3_R12_F32), b.to(torch.complex64)), w12)
         assert same(ops.mult_nn(ops.pack(a, ops.SU3_R12_F64), b), w12)
     assert seen == set(range(8))
+
+
+def test_soa_xcd_order_every_residue_exact(ops):
+    """The FP64 SoA product deals a row's site blocks out XCD-contiguously
+    when the plane stride (16 B x sites) lies within 128 KiB of a multiple of
+    4 MiB, padding the row's workgroup count to a multiple of 8. Site counts
+    2^18 + 128 k (+ 37) pick that order, with block counts of every residue
+    mod 8, ragged or not; every output must equal integer arithmetic, in
+    FP64 and (tile = workgroup index) FP32."""
+    rng = np.random.default_rng(818)
+    seen = set()
+    for k in range(8):
+        for r in (0, 37):
+            sites = 2 ** 18 + 128 * k + r
+            m = (16 * sites) % (4 << 20)
+            assert m < (128 << 10) or m > (4 << 20) - (128 << 10)
+            seen.add(-(-sites // 128) % 8)
+            say("exact SoA XCD order sites=%d" % sites)
+            a, b = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3))
+            want = _unembed(_embed(a) @ _embed(b)[None])
+            ta, tb = to_dev(a), to_dev(b)
+            for dt in (torch.complex128, torch.complex64):
+                sa = ops.aos_to_soa(ta.to(dt))
+                assert _same(ops.soa_to_aos(ops.mult_nn_soa(sa, tb.to(dt))), want)
+    assert seen == set(range(8))
