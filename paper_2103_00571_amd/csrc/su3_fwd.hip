@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
 // the same site offsets, plane stride n * elem_bytes apart. When that stride
 // is close to a multiple of 4 MiB (within 128 KiB), the planes of the one
 // window that tile = workgroup index streams collide in HBM and FP64 runs at
-// 0.89-0.93 of the site-major rate (sizes 2^20 +- 64, 2^20 + 4096, 3 * 2^19,
+// 0.88-0.93 of the site-major rate (sizes 2^20 +- 64, 2^20 + 4096, 3 * 2^19,
 // 2^21, 2^22); the XCD-contiguous order spreads the row over eight windows
 // and runs at 0.94-0.97 there, but at other strides it is 1-7% slower than
 // tile = workgroup index (sizes 24^4, 36^4, 40^4, 48^4, 56^4, 17 * 2^16). FP32
