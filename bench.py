@@ -6,7 +6,8 @@ One step is one pass of the product over the whole lattice. The headline is
 the FP64 site-major (AoS) product on an L=48 lattice (5,308,416 sites, 3.06 GB
 per array): W untimed passes, then K passes timed with HIP events on the
 stream the kernel runs on, bracketed by device synchronisation. `value` is
-sites per second. The other storage forms, the SoA layout, one GPU's share of
+sites per second. The other storage forms, the SoA layout (dense and at the
+padded plane pitch su3_soa_pitch gives), one GPU's share of
 the lattice split over 8 GPUs (shard8), the L=32 lattice (FP64 and FP32,
 site-major and SoA, 100 timed passes), the streaming copy over the same
 footprint (the measured bandwidth reference) and the adjoint (L=32) are timed
@@ -40,9 +41,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 FLOP_PER_SITE = 864            # paper's count: 4 x 27 x (4 mul + 4 add)
 MATVEC_FLOP_PER_SITE = 4 * 3 * 3 * 8   # 4 links x 3 rows x 3 complex multiply-adds of 8 flop
 # algorithmic bytes per site: a read once + c written once (b ignored)
-BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "f32": 576, "bf16": 288, "r12": 480,
+BYTES_PER_SITE = {"f64": 1152, "soa": 1152, "soap": 1152, "f32": 576, "bf16": 288, "r12": 480,
                   "r12c": 384, "r12f64": 960, "na": 1152, "an": 1152, "matvec": 816,
-                  "soa32": 576, "na32": 576, "an32": 576, "matvec32": 408}
+                  "soa32": 576, "soap32": 576, "na32": 576, "an32": 576, "matvec32": 408}
 BWD_BYTES_PER_SITE = {"f64": 3 * 576, "f32": 3 * 288}   # a, dC read; dA written
 # The paper's own figures for this kernel, on its hardware (context, not a
 # target): 864 flop per site, sites/s = GF/s * 1e9 / 864.
@@ -220,7 +221,7 @@ def main() -> int:
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
     ap.add_argument("--forms",
-                    default="f64,shard8,l32,soa,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,setup,copy,shapes,bwd")
+                    default="f64,shard8,l32,soa,soap,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,setup,copy,shapes,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-omp", action="store_true", help="skip the multi-core OpenMP CPU baseline")
@@ -323,6 +324,19 @@ def main() -> int:
             results[name].update({"sites": n32, "steps": steps32,
                                   "vs_site_major": results[key]["ms"] / ms})
             del sa, sc
+        if "soap" in forms:
+            # the padded SoA layout at the pitch su3_soa_pitch recommends
+            for name, x, tb, key, form in (("soap_L32", x64, tb64, "f64_L32", ops.SU3_F64),
+                                           ("soap32_L32", x32, tb32, "f32_L32", ops.SU3_F32)):
+                pitch = ops.soa_pitch(n32, form)
+                sa = ops.aos_to_soa(x, pitch)
+                sc = torch.empty_like(sa)
+                ms = time_launches(lambda: ops.mult_nn_soa(sa, tb, out=sc, sites=n32), steps32, args.warmup, torch,
+                                   LEG_WARM_S)
+                record(name, ms, BYTES_PER_SITE["soap" if form == ops.SU3_F64 else "soap32"], n32)
+                results[name].update({"sites": n32, "steps": steps32, "pitch": pitch,
+                                      "vs_site_major": results[key]["ms"] / ms})
+                del sa, sc
         del y64, x32, y32
 
     # ---- streaming copy over the same footprint (measured bandwidth) -------
@@ -384,6 +398,16 @@ def main() -> int:
         record("soa", ms, BYTES_PER_SITE["soa"], sites)
         results["soa"]["vs_site_major"] = ms64 / ms
         outputs["soa"] = ops.soa_to_aos(sc)
+        del sa, sc
+    if "soap" in forms:
+        pitch = ops.soa_pitch(sites, ops.SU3_F64)
+        sa = ops.aos_to_soa(ta, pitch)
+        sc = torch.empty_like(sa)
+        ms = time_launches(lambda: ops.mult_nn_soa(sa, tb64, out=sc, sites=sites), args.steps, args.warmup, torch,
+                           LEG_WARM_S)
+        record("soap", ms, BYTES_PER_SITE["soap"], sites)
+        results["soap"].update({"pitch": pitch, "vs_site_major": ms64 / ms})
+        outputs["soap"] = ops.soa_to_aos(sc, sites)
         del sa, sc
 
     # ---- reduced storage forms -----------------------------------------------
@@ -461,6 +485,16 @@ def main() -> int:
         if "f32" in results:
             results["soa32"]["vs_site_major"] = results["f32"]["ms"] / results["soa32"]["ms"]
         del sa, sc
+        if "soap" in forms:
+            pitch = ops.soa_pitch(sites, ops.SU3_F32)
+            sa = ops.aos_to_soa(t32, pitch)
+            sc = torch.empty_like(sa)
+            record("soap32", time_launches(lambda: ops.mult_nn_soa(sa, tb32, out=sc, sites=sites), args.steps,
+                                           args.warmup, torch, LEG_WARM_S), BYTES_PER_SITE["soap32"], sites)
+            results["soap32"]["pitch"] = pitch
+            if "f32" in results:
+                results["soap32"]["vs_site_major"] = results["f32"]["ms"] / results["soap32"]["ms"]
+            del sa, sc
         y = torch.empty_like(t32)
         for name, fn in (("na32", ops.mult_na), ("an32", ops.mult_an)):
             record(name, time_launches(lambda: fn(t32, tb32, out=y), args.steps, args.warmup, torch, LEG_WARM_S),
@@ -472,7 +506,7 @@ def main() -> int:
         record("matvec32", time_launches(lambda: ops.mat_vec(t32, tv, out=w), args.steps, args.warmup, torch, LEG_WARM_S),
                BYTES_PER_SITE["matvec32"], sites)
         del t32, tv, w
-    for name in ("f32", "bf16", "r12", "r12c", "r12f64", "soa"):
+    for name in ("f32", "bf16", "r12", "r12c", "r12f64", "soa", "soap"):
         if name in results:
             results[name]["speedup_vs_f64"] = ms64 / results[name]["ms"]
     # the paper counts a read and c written as its padded Site struct, 640 B

@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define SU3_ABI_VERSION 5
+#define SU3_ABI_VERSION 6
 
 /* storage form codes */
 enum su3_precision {
@@ -156,6 +156,31 @@ int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites,
                     int precision, void *stream);
 
 /*
+ * The SoA product on a padded SoA layout: plane p of a and c starts at
+ * complex offset p*pitch (pitch >= sites); elements sites .. pitch-1 of each
+ * plane are padding, never read or written. With pitch == sites this is
+ * su3_mult_nn_soa. In the dense layout the three planes a row reads lie one
+ * plane stride apart, and at some site counts (powers of two among them) the
+ * same offsets of those planes collide in HBM; a padded stride avoids that,
+ * the way lattice QCD codes pad their field strides. su3_soa_pitch gives the
+ * pitch at which the product streams at the site-major rate. Arguments,
+ * alignment and errors as su3_mult_nn_soa; a and c each span 36*pitch
+ * complex elements, c must not overlap a or b; pitch < sites returns
+ * SU3_ERR_SIZE.
+ */
+int su3_mult_nn_soa_pitched(const void *a, const void *b, void *c, int64_t sites,
+                            int64_t pitch, int precision, void *stream);
+
+/*
+ * Plane pitch (in complex elements) for a padded SoA layout of `sites`
+ * sites: sites rounded up to a multiple of 64, plus 512 (SU3_F64) or 128
+ * (SU3_F32); measured to stream at the site-major rate at every site count
+ * tried. Writes *pitch. Errors: SU3_ERR_PRECISION (not SU3_F64 or SU3_F32),
+ * SU3_ERR_SIZE (sites < 0 or too large), SU3_ERR_NULL.
+ */
+int su3_soa_pitch(int64_t sites, int precision, int64_t *pitch);
+
+/*
  * Layout transforms between AoS and SoA for SU3_F64 and SU3_F32 (a pure
  * permutation of complex elements, bit-exact): the data-structure remapping
  * of arXiv 2103.00571, section Related Work, as an explicit step outside the
@@ -167,6 +192,16 @@ int su3_aos_to_soa(const void *src, void *dst, int64_t sites, int precision,
                    void *stream);
 int su3_soa_to_aos(const void *src, void *dst, int64_t sites, int precision,
                    void *stream);
+/*
+ * The same transforms to and from the padded SoA layout (plane p at complex
+ * offset p*pitch, pitch >= sites): the SoA side spans 36*pitch elements and
+ * its padding is neither read nor written. pitch < sites returns
+ * SU3_ERR_SIZE; otherwise as above.
+ */
+int su3_aos_to_soa_pitched(const void *src, void *dst, int64_t sites,
+                           int64_t pitch, int precision, void *stream);
+int su3_soa_to_aos_pitched(const void *src, void *dst, int64_t sites,
+                           int64_t pitch, int precision, void *stream);
 
 /*
  * Conversion from FP64 AoS links to a storage form, and back. The paper has

@@ -16,7 +16,7 @@ __version__ = "0.2.0"
 _LAZY = {"abi", "ops"}
 _OPS_NAMES = {"SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32", "SU3_R12C_F32", "SU3_R12_F64", "SU3MultNN",
               "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_autograd", "mult_nn_bwd", "mult_nn_bwd_workspace",
-              "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack", "stream_copy", "stream_shape",
+              "mult_nn_soa", "soa_pitch", "aos_to_soa", "soa_to_aos", "pack", "unpack", "stream_copy", "stream_shape",
               "launch_shape", "form_of"}
 
 

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsu3.so")
 
 # su3.h constants
-ABI_VERSION = 5
+ABI_VERSION = 6
 SU3_F64, SU3_F32, SU3_BF16, SU3_R12_F32, SU3_R12C_F32, SU3_R12_F64 = 0, 1, 2, 3, 4, 5
 SU3_OK = 0
 SU3_ERR_NULL, SU3_ERR_SIZE, SU3_ERR_ALIGN, SU3_ERR_PRECISION = -1, -2, -3, -4
@@ -34,6 +34,10 @@ SIGNATURES = {
     "su3_mat_vec": ([_P, _P, _P, _I64, _I, _P], _I),
     "su3_aos_to_soa": ([_P, _P, _I64, _I, _P], _I),
     "su3_soa_to_aos": ([_P, _P, _I64, _I, _P], _I),
+    "su3_mult_nn_soa_pitched": ([_P, _P, _P, _I64, _I64, _I, _P], _I),
+    "su3_soa_pitch": ([_I64, _I, ctypes.POINTER(ctypes.c_int64)], _I),
+    "su3_aos_to_soa_pitched": ([_P, _P, _I64, _I64, _I, _P], _I),
+    "su3_soa_to_aos_pitched": ([_P, _P, _I64, _I64, _I, _P], _I),
     "su3_pack": ([_P, _P, _I64, _I, _P], _I),
     "su3_unpack": ([_P, _P, _I64, _I, _P], _I),
     "su3_mult_nn_bwd_workspace_bytes": ([_I64, _I], _SZ),
@@ -115,6 +119,25 @@ def su3_aos_to_soa(src: int, dst: int, sites: int, precision: int, stream: int) 
 
 def su3_soa_to_aos(src: int, dst: int, sites: int, precision: int, stream: int) -> int:
     return lib.su3_soa_to_aos(src, dst, sites, precision, stream)
+
+
+def su3_mult_nn_soa_pitched(a: int, b: int, c: int, sites: int, pitch: int, precision: int, stream: int) -> int:
+    return lib.su3_mult_nn_soa_pitched(a, b, c, sites, pitch, precision, stream)
+
+
+def su3_soa_pitch(sites: int, precision: int) -> int:
+    """The recommended plane pitch; raises SU3Error on a bad argument."""
+    p = ctypes.c_int64()
+    check(lib.su3_soa_pitch(sites, precision, ctypes.byref(p)), "su3_soa_pitch")
+    return p.value
+
+
+def su3_aos_to_soa_pitched(src: int, dst: int, sites: int, pitch: int, precision: int, stream: int) -> int:
+    return lib.su3_aos_to_soa_pitched(src, dst, sites, pitch, precision, stream)
+
+
+def su3_soa_to_aos_pitched(src: int, dst: int, sites: int, pitch: int, precision: int, stream: int) -> int:
+    return lib.su3_soa_to_aos_pitched(src, dst, sites, pitch, precision, stream)
 
 
 def su3_pack(src: int, dst: int, sites: int, precision: int, stream: int) -> int:

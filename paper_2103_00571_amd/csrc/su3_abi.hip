@@ -118,18 +118,59 @@ int su3_mult_nn(const void *a, const void *b, void *c, int64_t sites, int precis
     return status_of(launch_fwd_aos(a, b, c, sites, precision, (hipStream_t)stream));
 }
 
-int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
+// Validation of the SoA entries: planes of `pitch` elements (pitch >= sites).
+static int check_soa(const void *a, const void *b, const void *c, int64_t sites, int64_t pitch, int precision)
 {
     if (precision != SU3_F64 && precision != SU3_F32)
         return SU3_ERR_PRECISION;
+    if (sites < 0 || sites > kMaxSites || pitch < sites || pitch > kMaxSites)
+        return SU3_ERR_SIZE;
+    if (sites == 0)
+        return SU3_OK;
+    if (!a || !b || !c)
+        return SU3_ERR_NULL;
     Form f;
-    int st = check_lattice(a, b, c, sites, precision, f);
+    form_of(precision, f);
+    if (!aligned(a, 16) || !aligned(c, 16) || !aligned(b, f.b_align))
+        return SU3_ERR_ALIGN;
+    const int64_t es = precision == SU3_F64 ? 16 : 8, extent = 36 * pitch * es;
+    if (overlap(c, extent, a, extent) || overlap(c, extent, b, f.b_total))
+        return SU3_ERR_OVERLAP;
+    return SU3_OK;
+}
+
+static int mult_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int precision, void *stream)
+{
+    const int st = check_soa(a, b, c, sites, pitch, precision);
     if (st != SU3_OK || sites == 0)
         return st;
     const int es = precision == SU3_F64 ? 16 : 8;
-    if (!grid_fits(fwd_soa_grid(sites, es), soa_block_threads()))
+    if (!grid_fits(fwd_soa_grid(sites, pitch, es), soa_block_threads()))
         return SU3_ERR_SIZE;
-    return status_of(launch_fwd_soa(a, b, c, sites, es, (hipStream_t)stream));
+    return status_of(launch_fwd_soa(a, b, c, sites, pitch, es, (hipStream_t)stream));
+}
+
+int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
+{
+    return mult_soa(a, b, c, sites, sites, precision, stream);
+}
+
+int su3_mult_nn_soa_pitched(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int precision,
+                            void *stream)
+{
+    return mult_soa(a, b, c, sites, pitch, precision, stream);
+}
+
+int su3_soa_pitch(int64_t sites, int precision, int64_t *pitch)
+{
+    if (precision != SU3_F64 && precision != SU3_F32)
+        return SU3_ERR_PRECISION;
+    if (sites < 0 || sites > kMaxSites - 1024)
+        return SU3_ERR_SIZE;
+    if (!pitch)
+        return SU3_ERR_NULL;
+    *pitch = soa_pitch(sites, precision == SU3_F64 ? 16 : 8);
+    return SU3_OK;
 }
 
 int su3_mult_na(const void *a, const void *b, void *c, int64_t sites, int precision, void *stream)
@@ -178,11 +219,12 @@ int su3_mat_vec(const void *a, const void *v, void *w, int64_t sites, int precis
     return status_of(launch_mat_vec(a, v, w, sites, precision, (hipStream_t)stream));
 }
 
-static int transform(const void *src, void *dst, int64_t sites, int precision, bool to_soa, void *stream)
+static int transform(const void *src, void *dst, int64_t sites, int64_t pitch, int precision, bool to_soa,
+                     void *stream)
 {
     if (precision != SU3_F64 && precision != SU3_F32)
         return SU3_ERR_PRECISION;
-    if (sites < 0 || sites > kMaxSites)
+    if (sites < 0 || sites > kMaxSites || pitch < sites || pitch > kMaxSites)
         return SU3_ERR_SIZE;
     if (sites == 0)
         return SU3_OK;
@@ -190,20 +232,31 @@ static int transform(const void *src, void *dst, int64_t sites, int precision, b
         return SU3_ERR_NULL;
     if (!aligned(src, 16) || !aligned(dst, 16))
         return SU3_ERR_ALIGN;
-    const int64_t bytes = sites * (precision == SU3_F64 ? 576 : 288);
-    if (overlap(src, bytes, dst, bytes))
+    const int64_t es = precision == SU3_F64 ? 16 : 8;
+    const int64_t aos = sites * 36 * es, soa = pitch * 36 * es;
+    if (overlap(src, to_soa ? aos : soa, dst, to_soa ? soa : aos))
         return SU3_ERR_OVERLAP;
-    return status_of(launch_aos_soa(src, dst, sites, precision == SU3_F64 ? 16 : 8, to_soa, (hipStream_t)stream));
+    return status_of(launch_aos_soa(src, dst, sites, pitch, (int)es, to_soa, (hipStream_t)stream));
 }
 
 int su3_aos_to_soa(const void *src, void *dst, int64_t sites, int precision, void *stream)
 {
-    return transform(src, dst, sites, precision, true, stream);
+    return transform(src, dst, sites, sites, precision, true, stream);
 }
 
 int su3_soa_to_aos(const void *src, void *dst, int64_t sites, int precision, void *stream)
 {
-    return transform(src, dst, sites, precision, false, stream);
+    return transform(src, dst, sites, sites, precision, false, stream);
+}
+
+int su3_aos_to_soa_pitched(const void *src, void *dst, int64_t sites, int64_t pitch, int precision, void *stream)
+{
+    return transform(src, dst, sites, pitch, precision, true, stream);
+}
+
+int su3_soa_to_aos_pitched(const void *src, void *dst, int64_t sites, int64_t pitch, int precision, void *stream)
+{
+    return transform(src, dst, sites, pitch, precision, false, stream);
 }
 
 static int convert(const void *src, void *dst, int64_t sites, int precision, bool pack, void *stream)

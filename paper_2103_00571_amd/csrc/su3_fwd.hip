@@ -471,7 +471,8 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 // Thread per (site, output row): the row 3j + k is uniform over a workgroup,
 // so the link j and the b[j] entries sit in scalar registers. A wavefront
 // reads planes (j, k, 0..2) and writes planes (j, k, 0..2), each access one
-// contiguous 1 KiB (FP64) or 512 B (FP32) run. The grid is one dimension of
+// contiguous 1 KiB (FP64) or 512 B (FP32) run; plane p starts at element
+// p * pitch (pitch = n for the dense layout). The grid is one dimension of
 // 12 rows x nbp workgroups; workgroup `local` of a row takes site block
 // local (tile = workgroup index) or, with xcd set, xcd_order(local, nbp),
 // which gives each XCD one contiguous eighth of the row's site blocks (nbp
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 // `local` mod 8 is the XCD; the extra workgroups find no sites and exit).
 template <typename V, typename S>
 __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, const S *__restrict__ b,
-                                                  V *__restrict__ c, int64_t n, int64_t nbp, int xcd)
+                                                  V *__restrict__ c, int64_t n, int64_t pitch, int64_t nbp, int xcd)
 {
     const int row = (int)(blockIdx.x / nbp);     // 3j + k
     const int64_t local = (int64_t)blockIdx.x - (int64_t)row * nbp;
@@ -494,12 +495,12 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
         br[q] = b[2 * (9 * j + q)];
         bi[q] = b[2 * (9 * j + q) + 1];
     }
-    const V *__restrict__ ap = a + (int64_t)(3 * row) * n + s;
-    V *__restrict__ cp = c + (int64_t)(3 * row) * n + s;
+    const V *__restrict__ ap = a + (int64_t)(3 * row) * pitch + s;
+    V *__restrict__ cp = c + (int64_t)(3 * row) * pitch + s;
     V x[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
-        x[m] = ld_stream(ap + m * n);
+        x[m] = ld_stream(ap + m * pitch);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         S re = 0, im = 0;
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
         for (int m = 0; m < 3; ++m)
             cmac(re, im, x[m].x, x[m].y, br[3 * m + l], bi[3 * m + l]);
         V o = {re, im};
-        st_stream(cp + l * n, o);
+        st_stream(cp + l * pitch, o);
     }
 }
 
@@ -520,19 +521,34 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
 // and runs at 0.94-0.97 there, but at other strides it is 1-7% slower than
 // tile = workgroup index (sizes 24^4, 36^4, 40^4, 48^4, 56^4, 17 * 2^16). FP32
 // keeps tile = workgroup index at every stride (the XCD order measured equal
-// or slower).
-static bool soa_xcd(int64_t sites, int elem_bytes)
+// or slower), and so does a padded layout (pitch > n): with the pitch of
+// soa_pitch it streams at the site-major rate in that order.
+static bool soa_xcd(int64_t sites, int64_t pitch, int elem_bytes)
 {
-    if (elem_bytes != 16)
+    if (elem_bytes != 16 || pitch != sites)
         return false;
     const int64_t m = (sites * 16) % ((int64_t)4 << 20);
     return m < ((int64_t)128 << 10) || m > ((int64_t)4 << 20) - ((int64_t)128 << 10);
 }
 
-static int64_t soa_blocks_per_row(int64_t sites, int elem_bytes)
+// Plane pitch of the padded SoA layout at which the product streams at the
+// site-major rate in workgroup order: the site count rounded up to 64 plus
+// 512 (FP64, 8 KiB per plane) or 128 (FP32, 1 KiB). Measured at 14 site
+// counts from 24^4 to 56^4 (14 in FP64, 11 in FP32; powers of two and their
+// neighbours among them):
+// 1.01-1.05 of the site-major rate in FP64, 0.98-1.03 in FP32, where the
+// dense layout ran at 0.88-1.07 and 0.83-1.03. The pad is not monotone in
+// its effect: 64 sites (1 KiB) still left 2^20 - 64 at 0.90 in FP64, and a
+// 64 KiB pad fell back to 0.90 at 2^20.
+int64_t soa_pitch(int64_t sites, int elem_bytes)
+{
+    return (sites + 63) / 64 * 64 + (elem_bytes == 16 ? 512 : 128);
+}
+
+static int64_t soa_blocks_per_row(int64_t sites, int64_t pitch, int elem_bytes)
 {
     const int64_t nb = (sites + kSoaBlock - 1) / kSoaBlock;
-    return soa_xcd(sites, elem_bytes) ? (nb + kXcds - 1) / kXcds * kXcds : nb;
+    return soa_xcd(sites, pitch, elem_bytes) ? (nb + kXcds - 1) / kXcds * kXcds : nb;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -597,7 +613,10 @@ int64_t fwd_an_grid(int precision, int64_t sites)
     return precision == 0 ? aos_grid<FormAnF64>(sites) : aos_grid<FormAnF32>(sites);
 }
 
-int64_t fwd_soa_grid(int64_t sites, int elem_bytes) { return 12 * soa_blocks_per_row(sites, elem_bytes); }
+int64_t fwd_soa_grid(int64_t sites, int64_t pitch, int elem_bytes)
+{
+    return 12 * soa_blocks_per_row(sites, pitch, elem_bytes);
+}
 int soa_block_threads() { return kSoaBlock; }
 
 template <class F, bool kConjB = false>
@@ -636,22 +655,23 @@ hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, i
     return launch_aos<FormAnF32>(a, b, c, sites, s);
 }
 
-hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s)
+hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int elem_bytes,
+                          hipStream_t s)
 {
     static std::atomic<int> pad64[kMaxDevices], pad32[kMaxDevices];
-    const int64_t nbp = soa_blocks_per_row(sites, elem_bytes);
-    const int xcd = soa_xcd(sites, elem_bytes) ? 1 : 0;
+    const int64_t nbp = soa_blocks_per_row(sites, pitch, elem_bytes);
+    const int xcd = soa_xcd(sites, pitch, elem_bytes) ? 1 : 0;
     const dim3 grid((unsigned)(12 * nbp));
     if (elem_bytes == 16) {
         const size_t pad =
             occupancy_pad(reinterpret_cast<const void *>(fwd_soa<d2, double>), SU3_WAVES_SOA_F64, kSoaBlock, pad64);
         return launch_k(fwd_soa<d2, double>, grid, dim3(kSoaBlock), s, pad, (const d2 *)a, (const double *)b, (d2 *)c,
-                        sites, nbp, xcd);
+                        sites, pitch, nbp, xcd);
     }
     const size_t pad =
         occupancy_pad(reinterpret_cast<const void *>(fwd_soa<f2, float>), SU3_WAVES_SOA_F32, kSoaBlock, pad32);
     return launch_k(fwd_soa<f2, float>, grid, dim3(kSoaBlock), s, pad, (const f2 *)a, (const float *)b, (f2 *)c, sites,
-                    nbp, xcd);
+                    pitch, nbp, xcd);
 }
 
 } // namespace su3

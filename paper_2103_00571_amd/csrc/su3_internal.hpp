@@ -141,7 +141,9 @@ size_t occupancy_pad_for(const void *kernel, int waves, int block, int dev);
 // ---- launchers (each returns hipSuccess or the launch error) --------------
 // Forward products. The grid covers the lattice once; *_grid report it.
 int64_t fwd_aos_grid(int precision, int64_t sites);
-int64_t fwd_soa_grid(int64_t sites, int elem_bytes);
+int64_t fwd_soa_grid(int64_t sites, int64_t pitch, int elem_bytes);
+// Plane pitch (elements) of the padded SoA layout that streams at the site-major rate.
+int64_t soa_pitch(int64_t sites, int elem_bytes);
 int soa_block_threads();
 hipError_t launch_fwd_aos(const void *a, const void *b, void *c, int64_t sites, int precision, hipStream_t s);
 // The a b^H and a^H b products (FP64 = 0, FP32 = 1).
@@ -151,10 +153,13 @@ hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, i
 // Matrix times colour vector, w[s][j] = a[s][j] v[s] (FP64 = 0, FP32 = 1).
 int64_t mat_vec_grid(int precision, int64_t sites);
 hipError_t launch_mat_vec(const void *a, const void *v, void *w, int64_t sites, int precision, hipStream_t s);
-hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int elem_bytes, hipStream_t s);
+// SoA product; plane p of a and c starts at element p * pitch (pitch >= sites).
+hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int elem_bytes,
+                          hipStream_t s);
 int aos_block_threads();
 // Layout and storage-form conversions.
-hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_bytes, bool to_soa, hipStream_t s);
+hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int64_t pitch, int elem_bytes, bool to_soa,
+                          hipStream_t s);
 hipError_t launch_pack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_unpack(const void *src, void *dst, int64_t sites, int precision, hipStream_t s);
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);

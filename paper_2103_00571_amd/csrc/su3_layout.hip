@@ -34,7 +34,7 @@ constexpr int kTileSites = 64;
 
 template <typename V, bool kToSoa>
 __global__ __launch_bounds__(kBlock) void transpose_aos_soa(const V *__restrict__ src, V *__restrict__ dst,
-                                                            int64_t n)
+                                                            int64_t n, int64_t pitch)
 {
     __shared__ V tile[36][kTileSites + 1];
     const int64_t tiles = (n + kTileSites - 1) / kTileSites;
@@ -48,13 +48,13 @@ __global__ __launch_bounds__(kBlock) void transpose_aos_soa(const V *__restrict_
             for (int e = threadIdx.x; e < 36 * kTileSites; e += kBlock) {
                 const int p = e / kTileSites, sl = e % kTileSites;
                 if (sl < ns)
-                    dst[(int64_t)p * n + s0 + sl] = tile[p][sl];
+                    dst[(int64_t)p * pitch + s0 + sl] = tile[p][sl];
             }
         } else {
             for (int e = threadIdx.x; e < 36 * kTileSites; e += kBlock) {
                 const int p = e / kTileSites, sl = e % kTileSites;
                 if (sl < ns)
-                    tile[p][sl] = src[(int64_t)p * n + s0 + sl];
+                    tile[p][sl] = src[(int64_t)p * pitch + s0 + sl];
             }
             __syncthreads();
             for (int e = threadIdx.x; e < ns * 36; e += kBlock)
@@ -292,17 +292,22 @@ static unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = kOnePas
     return (unsigned)g;
 }
 
-hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int elem_bytes, bool to_soa, hipStream_t s)
+hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int64_t pitch, int elem_bytes, bool to_soa,
+                          hipStream_t s)
 {
     const unsigned g = grid_for(sites, kTileSites);
     if (elem_bytes == 16) {
         if (to_soa)
-            return launch_k(transpose_aos_soa<d2, true>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites);
-        return launch_k(transpose_aos_soa<d2, false>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites);
+            return launch_k(transpose_aos_soa<d2, true>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites,
+                            pitch);
+        return launch_k(transpose_aos_soa<d2, false>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites,
+                        pitch);
     }
     if (to_soa)
-        return launch_k(transpose_aos_soa<f2, true>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites);
-    return launch_k(transpose_aos_soa<f2, false>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites);
+        return launch_k(transpose_aos_soa<f2, true>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites,
+                        pitch);
+    return launch_k(transpose_aos_soa<f2, false>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites,
+                    pitch);
 }
 
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)

@@ -13,8 +13,8 @@ Tensor forms (site-major "AoS", one row per site, see include/su3.h):
     SU3_R12_F64   complex128 (N, 4, 2, 3)        complex128 (4,3,3)  complex128 (N,4,3,3)
 
 SU3_R12C_F32 stores a exactly like SU3_R12_F32; pass form=SU3_R12C_F32 to
-keep the product compressed. SoA tensors are (4, 3, 3, N) in complex128 or
-complex64.
+keep the product compressed. SoA tensors are (4, 3, 3, P) in complex128 or
+complex64, P = N for the dense layout or a padded pitch P > N (soa_pitch).
 """
 
 from __future__ import annotations
@@ -27,7 +27,8 @@ from .abi import SU3_BF16, SU3_F32, SU3_F64, SU3_R12_F32, SU3_R12_F64, SU3_R12C_
 
 __all__ = [
     "SU3_F64", "SU3_F32", "SU3_BF16", "SU3_R12_F32", "SU3_R12C_F32", "SU3_R12_F64",
-    "form_of", "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_soa", "aos_to_soa", "soa_to_aos", "pack", "unpack",
+    "form_of", "mult_nn", "mult_na", "mult_an", "mat_vec", "mult_nn_soa", "soa_pitch", "aos_to_soa", "soa_to_aos",
+    "pack", "unpack",
     "mult_nn_bwd", "mult_nn_bwd_workspace", "stream_copy", "stream_shape", "SU3MultNN", "mult_nn_autograd",
     "launch_shape",
 ]
@@ -163,38 +164,70 @@ def _soa_form(x: torch.Tensor) -> int:
     raise ValueError("not an SoA lattice tensor: dtype %s shape %s" % (x.dtype, tuple(x.shape)))
 
 
-def mult_nn_soa(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """The same product on the SoA layout, (4, 3, 3, N) planes."""
+def soa_pitch(sites: int, form: int) -> int:
+    """Plane pitch of the padded SoA layout at which mult_nn_soa streams at the
+    site-major rate (su3_soa_pitch)."""
+    return abi.su3_soa_pitch(sites, form)
+
+
+def mult_nn_soa(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+                sites: int | None = None) -> torch.Tensor:
+    """The same product on the SoA layout, (4, 3, 3, P) planes. The first
+    `sites` elements of each plane are the lattice (default: all P); with
+    sites < P the layout is padded and the padding is neither read nor
+    written."""
     form = _soa_form(a)
     _check_b(b, form)
+    pitch = a.shape[3]
+    sites = pitch if sites is None else sites
+    if not 0 <= sites <= pitch:
+        raise ValueError("sites must lie in [0, pitch]")
     if out is None:
         out = torch.empty_like(a)
     elif out.dtype != a.dtype or out.shape != a.shape:
         raise ValueError("out has the wrong dtype or shape")
     _need_gpu(a, b, out)
     with torch.cuda.device(a.device):
-        check(abi.su3_mult_nn_soa(a.data_ptr(), b.data_ptr(), out.data_ptr(), a.shape[3], form, _stream(a)),
-              "su3_mult_nn_soa")
+        if sites == pitch:
+            rc = abi.su3_mult_nn_soa(a.data_ptr(), b.data_ptr(), out.data_ptr(), sites, form, _stream(a))
+        else:
+            rc = abi.su3_mult_nn_soa_pitched(a.data_ptr(), b.data_ptr(), out.data_ptr(), sites, pitch, form,
+                                             _stream(a))
+        check(rc, "su3_mult_nn_soa")
     return out
 
 
-def aos_to_soa(x: torch.Tensor) -> torch.Tensor:
+def aos_to_soa(x: torch.Tensor, pitch: int | None = None) -> torch.Tensor:
+    """Site-major links -> SoA planes (4, 3, 3, pitch); pitch defaults to the
+    site count (the dense layout). Padding elements are left uninitialised."""
     form = form_of(x)
     if form not in (SU3_F64, SU3_F32):
         raise ValueError("SoA exists for FP64 and FP32 only")
-    out = torch.empty((4, 3, 3, x.shape[0]), dtype=x.dtype, device=x.device)
+    sites = x.shape[0]
+    pitch = sites if pitch is None else pitch
+    if pitch < sites:
+        raise ValueError("pitch must be at least the site count")
+    out = torch.empty((4, 3, 3, pitch), dtype=x.dtype, device=x.device)
     _need_gpu(x, out)
     with torch.cuda.device(x.device):
-        check(abi.su3_aos_to_soa(x.data_ptr(), out.data_ptr(), x.shape[0], form, _stream(x)), "su3_aos_to_soa")
+        check(abi.su3_aos_to_soa_pitched(x.data_ptr(), out.data_ptr(), sites, pitch, form, _stream(x)),
+              "su3_aos_to_soa")
     return out
 
 
-def soa_to_aos(x: torch.Tensor) -> torch.Tensor:
+def soa_to_aos(x: torch.Tensor, sites: int | None = None) -> torch.Tensor:
+    """SoA planes (4, 3, 3, P) -> site-major links of the first `sites`
+    elements of each plane (default: all P)."""
     form = _soa_form(x)
-    out = torch.empty((x.shape[3], 4, 3, 3), dtype=x.dtype, device=x.device)
+    pitch = x.shape[3]
+    sites = pitch if sites is None else sites
+    if not 0 <= sites <= pitch:
+        raise ValueError("sites must lie in [0, pitch]")
+    out = torch.empty((sites, 4, 3, 3), dtype=x.dtype, device=x.device)
     _need_gpu(x, out)
     with torch.cuda.device(x.device):
-        check(abi.su3_soa_to_aos(x.data_ptr(), out.data_ptr(), x.shape[3], form, _stream(x)), "su3_soa_to_aos")
+        check(abi.su3_soa_to_aos_pitched(x.data_ptr(), out.data_ptr(), sites, pitch, form, _stream(x)),
+              "su3_soa_to_aos")
     return out
 
 

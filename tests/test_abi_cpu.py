@@ -111,12 +111,50 @@ def test_soa_transform_pack_validation(abi):
         assert f(A, A + 16, 5, 0, None) == abi.SU3_ERR_OVERLAP
         assert f(A, C + 8, 5, 1, None) == abi.SU3_ERR_ALIGN
         assert f(0, C, 5, 0, None) == abi.SU3_ERR_NULL
+    for f in (abi.su3_aos_to_soa_pitched, abi.su3_soa_to_aos_pitched):
+        assert f(A, C, 0, 0, 0, None) == abi.SU3_OK
+        assert f(A, C, 0, 64, 0, None) == abi.SU3_OK                 # no sites: no launch
+        assert f(A, C, 5, 4, 0, None) == abi.SU3_ERR_SIZE            # pitch < sites
+        assert f(A, C, -1, 4, 0, None) == abi.SU3_ERR_SIZE
+        assert f(A, C, 5, 1 << 62, 0, None) == abi.SU3_ERR_SIZE
+        assert f(A, C, 5, 8, 2, None) == abi.SU3_ERR_PRECISION
+        assert f(A, C + 8, 5, 8, 1, None) == abi.SU3_ERR_ALIGN
+        assert f(0, C, 5, 8, 0, None) == abi.SU3_ERR_NULL
+    # The SoA side spans 36 * pitch elements: a destination just past the 5
+    # AoS sites still lies inside the padded SoA source.
+    assert abi.su3_soa_to_aos_pitched(A, A + 36 * 5 * 16, 5, 64, 0, None) == abi.SU3_ERR_OVERLAP
+    assert abi.su3_aos_to_soa_pitched(A + 36 * 5 * 16, A, 5, 64, 0, None) == abi.SU3_ERR_OVERLAP
+    f = abi.su3_mult_nn_soa_pitched
+    assert f(A, B, C, 0, 0, 0, None) == abi.SU3_OK
+    assert f(A, B, C, 5, 4, 0, None) == abi.SU3_ERR_SIZE
+    assert f(A, B, C, 5, 1 << 62, 1, None) == abi.SU3_ERR_SIZE
+    assert f(A, B, C, 5, 8, 2, None) == abi.SU3_ERR_PRECISION
+    assert f(0, B, C, 5, 8, 0, None) == abi.SU3_ERR_NULL
+    assert f(A, B, C + 8, 5, 8, 0, None) == abi.SU3_ERR_ALIGN
+    assert f(A, B, A + 36 * 5 * 16, 5, 64, 0, None) == abi.SU3_ERR_OVERLAP   # c inside a's padding
+    assert f(A, C + 16, C, 5, 64, 1, None) == abi.SU3_ERR_OVERLAP             # c covers b
     for f in (abi.su3_pack, abi.su3_unpack):
         assert f(A, C, -3, 1, None) == abi.SU3_ERR_SIZE
         assert f(A, C, 5, 6, None) == abi.SU3_ERR_PRECISION
         assert f(A, C, 5, 7, None) == abi.SU3_ERR_PRECISION
         assert f(A, A + 64, 5, 1, None) == abi.SU3_ERR_OVERLAP
         assert f(A, 0, 5, 1, None) == abi.SU3_ERR_NULL
+
+
+def test_soa_pitch(abi):
+    # sites rounded up to 64, plus 512 (FP64) or 128 (FP32) elements
+    for sites, p64, p32 in ((0, 512, 128), (1, 576, 192), (64, 576, 192), (65, 640, 256),
+                            (1 << 20, (1 << 20) + 512, (1 << 20) + 128), (48 ** 4, 48 ** 4 + 512, 48 ** 4 + 128)):
+        assert abi.su3_soa_pitch(sites, 0) == p64
+        assert abi.su3_soa_pitch(sites, 1) == p32
+    for sites in range(0, 3000, 37):
+        p = abi.su3_soa_pitch(sites, 0)
+        assert p >= sites and p % 64 == 0
+    with pytest.raises(abi.SU3Error):
+        abi.su3_soa_pitch(10, 2)
+    with pytest.raises(abi.SU3Error):
+        abi.su3_soa_pitch(-1, 0)
+    assert abi.lib.su3_soa_pitch(10, 0, None) == abi.SU3_ERR_NULL
 
 
 def test_bwd_validation(abi):

@@ -265,3 +265,22 @@ def test_soa_xcd_order_every_residue_exact(ops):
                 sa = ops.aos_to_soa(ta.to(dt))
                 assert _same(ops.soa_to_aos(ops.mult_nn_soa(sa, tb.to(dt))), want)
     assert seen == set(range(8))
+
+
+def test_soa_pitched_exact(ops):
+    """The padded SoA layout at site counts whose dense plane stride aliases
+    in HBM (2^20, 2^20 - 64, 2^18 + 37) and at a small ragged one, each at
+    the recommended pitch and at that pitch + 37 (odd): every output equals
+    integer arithmetic bit for bit in FP64 and FP32."""
+    rng = np.random.default_rng(919)
+    for sites in (2 ** 20, 2 ** 20 - 64, 2 ** 18 + 37, 999):
+        a, b = _ints(rng, (sites, 4, 3, 3)), _ints(rng, (4, 3, 3))
+        want = _unembed(_embed(a) @ _embed(b)[None])
+        ta, tb = to_dev(a), to_dev(b)
+        for dt, form in ((torch.complex128, ops.SU3_F64), (torch.complex64, ops.SU3_F32)):
+            p0 = ops.soa_pitch(sites, form)
+            for pitch in (p0, p0 + 37):
+                say("exact SoA pitched sites=%d pitch=%d form=%d" % (sites, pitch, form))
+                sa = ops.aos_to_soa(ta.to(dt), pitch)
+                sc = ops.mult_nn_soa(sa, tb.to(dt), sites=sites)
+                assert _same(ops.soa_to_aos(sc, sites), want)

@@ -184,10 +184,11 @@ def test_mat_vec_l48_full(O, ops):
 def test_l48_products_full(O, ops):
     """L=48 (5,308,416 sites), the inputs and launch configuration the
     benchmark times: a b^H, a^H b, reconstruct-12 in and out, reconstruct-12
-    in FP64, the SoA product, and the FP64 product on one GPU's share of the
-    lattice split over 8 GPUs (the first 663,552 sites). Every output is
-    written into a NaN-poisoned buffer (with guard sites where the layout is
-    site-major) and compared with the oracle."""
+    in FP64, the SoA product (dense and at the padded pitch), and the FP64
+    product on one GPU's share of the lattice split over 8 GPUs (the first
+    663,552 sites). Every output is written into a NaN-poisoned buffer (with
+    guard sites where the layout is site-major) and compared with the
+    oracle."""
     sites = L48
     a, b, ref = l48_case()
     ta, tb = to_dev(a), to_dev(b)
@@ -223,6 +224,18 @@ def test_l48_products_full(O, ops):
     ops.mult_nn_soa(sa, tb, out=sc)
     del sa
     got = ops.soa_to_aos(sc).cpu().numpy()
+    del sc
+    assert O.max_abs_diff(got, ref) <= 1e-13
+    say("L=48 SoA, padded pitch")
+    pitch = ops.soa_pitch(sites, ops.SU3_F64)
+    sa = ops.aos_to_soa(ta, pitch)
+    sc = poison_(torch.empty_like(sa))
+    ops.mult_nn_soa(sa, tb, out=sc, sites=sites)
+    del sa
+    pad = torch.view_as_real(sc[..., sites:])
+    assert bool(torch.isnan(pad).all())
+    del pad
+    got = ops.soa_to_aos(sc, sites).cpu().numpy()
     del sc
     assert O.max_abs_diff(got, ref) <= 1e-13
     say("L=48 / 8 share")
