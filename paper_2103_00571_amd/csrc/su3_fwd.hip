@@ -533,13 +533,14 @@ static bool soa_xcd(int64_t sites, int64_t pitch, int elem_bytes)
 
 // Plane pitch of the padded SoA layout at which the product streams at the
 // site-major rate in workgroup order: the site count rounded up to 64 plus
-// 512 (FP64, 8 KiB per plane) or 128 (FP32, 1 KiB). Measured at 14 site
-// counts from 24^4 to 56^4 (14 in FP64, 11 in FP32; powers of two and their
-// neighbours among them):
-// 1.01-1.05 of the site-major rate in FP64, 0.98-1.03 in FP32, where the
-// dense layout ran at 0.88-1.07 and 0.83-1.03. The pad is not monotone in
-// its effect: 64 sites (1 KiB) still left 2^20 - 64 at 0.90 in FP64, and a
-// 64 KiB pad fell back to 0.90 at 2^20.
+// 512 (FP64, 8 KiB per plane) or 128 (FP32, 1 KiB). Measured on random data
+// at 14 site counts from 24^4 to 56^4 (powers of two and their neighbours
+// among them), as the SoA rate over the site-major rate: 0.976-1.031 (mean
+// 0.996) in FP64 and 0.972-1.020 (mean 0.994) in FP32, where the dense layout
+// ran at 0.934-1.020 (0.981) and 0.845-1.024 (0.957). The pad is not monotone
+// in its effect, and no fixed residue of the plane stride mod 64 KiB did as
+// well at every size: a 1 KiB FP64 stride residue left 2^20 - 64 at 0.89,
+// and 16 KiB left 2^20 at 0.86.
 int64_t soa_pitch(int64_t sites, int elem_bytes)
 {
     return (sites + 63) / 64 * 64 + (elem_bytes == 16 ? 512 : 128);
