@@ -1,10 +1,12 @@
 // su3_c_api.cpp -- calling libsu3 through its C ABI alone (no Python, no
 // torch): device buffers from hipMalloc, a HIP stream, the forward product
-// in FP64 and the adjoint with its caller-owned workspace.
+// in FP64, the adjoint with its caller-owned workspace, and the product on
+// the padded SoA layout at the pitch the library recommends.
 //
 // With b[j] = I every product is an exact copy, so the program can check its
-// results without any reference implementation: c must equal a bit for bit,
-// and dA = dC b^H must equal dC bit for bit. The entries of a and dC are
+// results without any reference implementation: c must equal a bit for bit
+// (also after AoS -> padded SoA, the SoA product and back), and dA = dC b^H
+// must equal dC bit for bit. The entries of a and dC are
 // small integers, so every partial sum of dB = sum_s a^H dC is an integer
 // below 2^53 and exact in FP64: dB must equal the same sum formed in int64
 // on the host. Exit status 0 and "ok" on success; the status string of the
@@ -116,9 +118,34 @@ int main(int argc, char **argv)
             std::fprintf(stderr, "dB[%d] = %.17g, exact sum %lld\n", q, db[q], (long long)want[q]);
             return 7;
         }
-    for (void *p : {(void *)d_a, (void *)d_b, (void *)d_c, (void *)d_dc, (void *)d_da, (void *)d_db, d_ws})
+
+    // The padded SoA layout: plane p at complex offset p * pitch. a -> SoA,
+    // c = a b on the SoA planes, c -> site-major; with b = I that is a again.
+    int64_t pitch = 0;
+    SU3_OK_OR_FAIL(su3_soa_pitch(sites, SU3_F64, &pitch));
+    if (pitch < sites) {
+        std::fprintf(stderr, "pitch %lld < sites\n", (long long)pitch);
+        return 8;
+    }
+    const size_t soa_bytes = (size_t)pitch * 36 * 2 * sizeof(double);
+    double *d_sa, *d_sc;
+    HIP_OK(hipMalloc((void **)&d_sa, soa_bytes));
+    HIP_OK(hipMalloc((void **)&d_sc, soa_bytes));
+    HIP_OK(hipMemsetAsync(d_c, 0, bytes, stream));
+    SU3_OK_OR_FAIL(su3_aos_to_soa_pitched(d_a, d_sa, sites, pitch, SU3_F64, stream));
+    SU3_OK_OR_FAIL(su3_mult_nn_soa_pitched(d_sa, d_b, d_sc, sites, pitch, SU3_F64, stream));
+    SU3_OK_OR_FAIL(su3_soa_to_aos_pitched(d_sc, d_c, sites, pitch, SU3_F64, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    HIP_OK(hipMemcpy(out.data(), d_c, bytes, hipMemcpyDeviceToHost));
+    if (std::memcmp(out.data(), a.data(), bytes) != 0) {
+        std::fprintf(stderr, "padded SoA round trip of c = a b != a for b = I\n");
+        return 9;
+    }
+    for (void *p : {(void *)d_a, (void *)d_b, (void *)d_c, (void *)d_dc, (void *)d_da, (void *)d_db, d_ws,
+                    (void *)d_sa, (void *)d_sc})
         HIP_OK(hipFree(p));
     HIP_OK(hipStreamDestroy(stream));
-    std::printf("ok: %lld sites, forward and adjoint (dA and dB) through the C ABI\n", (long long)sites);
+    std::printf("ok: %lld sites, forward, adjoint (dA and dB) and padded SoA (pitch %lld) through the C ABI\n",
+                (long long)sites, (long long)pitch);
     return 0;
 }

@@ -1,7 +1,8 @@
 """The C ABI used from C++ alone: the example program (built with the
-library) allocates with hipMalloc, runs the FP64 forward product and the
-adjoint on a HIP stream, checks the exact b = I results and a rejected
-in-place call, and prints "ok"."""
+library) allocates with hipMalloc, runs the FP64 forward product, the
+adjoint and the product on the padded SoA layout (AoS -> SoA at the
+recommended pitch, the SoA product, back) on a HIP stream, checks the exact
+b = I results and a rejected in-place call, and prints "ok"."""
 
 import os
 import subprocess
