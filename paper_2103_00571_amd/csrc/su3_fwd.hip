@@ -478,7 +478,13 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 // which gives each XCD one contiguous eighth of the row's site blocks (nbp
 // is then the row's block count rounded up to a multiple of 8, so that
 // `local` mod 8 is the XCD; the extra workgroups find no sites and exit).
-template <typename V, typename S>
+// kPhases splits a thread's three plane loads into phases (soa_phases): 1
+// issues them together; 2 issues planes 0 and 1, then waits for them before
+// it issues plane 2; 3 waits after every plane. A wait is an empty asm
+// statement that takes the accumulators as inputs, so every load before it
+// has completed and no later load moves above it. The arithmetic and its
+// order are the same in every phase count, so the output is bit-identical.
+template <typename V, typename S, int kPhases>
 __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, const S *__restrict__ b,
                                                   V *__restrict__ c, int64_t n, int64_t pitch, int64_t nbp, int xcd)
 {
@@ -497,17 +503,19 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
     }
     const V *__restrict__ ap = a + (int64_t)(3 * row) * pitch + s;
     V *__restrict__ cp = c + (int64_t)(3 * row) * pitch + s;
-    V x[3];
+    S re[3] = {0, 0, 0}, im[3] = {0, 0, 0};
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
-        x[m] = ld_stream(ap + m * pitch);
+    for (int m = 0; m < 3; ++m) {
+        const V x = ld_stream(ap + m * pitch);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            cmac(re[l], im[l], x.x, x.y, br[3 * m + l], bi[3 * m + l]);
+        if ((kPhases == 3 && m < 2) || (kPhases == 2 && m == 1))
+            asm volatile("" ::"v"(re[0]), "v"(im[0]), "v"(re[1]), "v"(im[1]), "v"(re[2]), "v"(im[2]) : "memory");
+    }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        S re = 0, im = 0;
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-            cmac(re, im, x[m].x, x[m].y, br[3 * m + l], bi[3 * m + l]);
-        V o = {re, im};
+        V o = {re[l], im[l]};
         st_stream(cp + l * pitch, o);
     }
 }
@@ -529,6 +537,31 @@ static bool soa_xcd(int64_t sites, int64_t pitch, int elem_bytes)
         return false;
     const int64_t m = (sites * 16) % ((int64_t)4 << 20);
     return m < ((int64_t)128 << 10) || m > ((int64_t)4 << 20) - ((int64_t)128 << 10);
+}
+
+// Load phases of the SoA product (fwd_soa). When all of a thread's plane
+// loads are in flight together, the workgroups that run at once read the
+// three planes of a row at the same site window, one plane stride apart, and
+// at some strides those reads collide in HBM. Waiting between phases makes a
+// workgroup's planes arrive one after another, so at any moment the
+// resident workgroups, which started at different times, read different
+// planes at different site offsets. That costs bytes in flight per
+// wavefront. FP32 (no occupancy cap) gains, measured on random data at 16 site
+// counts from 24^4 to 56^4. Stock kernel: 0.84-1.05 of the site-major rate
+// (mean 0.954). Two phases: 0.88-1.04 (0.981). Three phases are best where
+// the plane stride is a multiple of 8 MiB and at least 16 MiB: 0.92-0.98
+// there, against 0.84-0.95 for the stock kernel and 0.88-0.98 for two
+// phases. FP64 keeps one phase: with its occupancy cap of 8 wavefronts the
+// phased kernel lost up to a third, and with caps of 16 or 24 it was 1-2%
+// slower on average. The padded layout keeps one phase too: its stride does
+// not collide.
+static int soa_phases(int64_t sites, int64_t pitch, int elem_bytes)
+{
+    if (elem_bytes != 8 || pitch != sites)
+        return 1;
+    const int64_t stride = sites * 8, m8 = stride % ((int64_t)8 << 20);
+    const bool on8 = m8 < ((int64_t)128 << 10) || m8 > ((int64_t)8 << 20) - ((int64_t)128 << 10);
+    return on8 && stride >= ((int64_t)16 << 20) - ((int64_t)128 << 10) ? 3 : 2;
 }
 
 // Plane pitch of the padded SoA layout at which the product streams at the
@@ -656,23 +689,30 @@ hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, i
     return launch_aos<FormAnF32>(a, b, c, sites, s);
 }
 
+template <typename V, typename S, int kPhases>
+static hipError_t launch_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int waves,
+                             hipStream_t s)
+{
+    static std::atomic<int> pad_cache[kMaxDevices];
+    const int es = (int)sizeof(V);
+    const int64_t nbp = soa_blocks_per_row(sites, pitch, es);
+    const int xcd = soa_xcd(sites, pitch, es) ? 1 : 0;
+    const size_t pad =
+        occupancy_pad(reinterpret_cast<const void *>(fwd_soa<V, S, kPhases>), waves, kSoaBlock, pad_cache);
+    return launch_k(fwd_soa<V, S, kPhases>, dim3((unsigned)(12 * nbp)), dim3(kSoaBlock), s, pad, (const V *)a,
+                    (const S *)b, (V *)c, sites, pitch, nbp, xcd);
+}
+
 hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int elem_bytes,
                           hipStream_t s)
 {
-    static std::atomic<int> pad64[kMaxDevices], pad32[kMaxDevices];
-    const int64_t nbp = soa_blocks_per_row(sites, pitch, elem_bytes);
-    const int xcd = soa_xcd(sites, pitch, elem_bytes) ? 1 : 0;
-    const dim3 grid((unsigned)(12 * nbp));
-    if (elem_bytes == 16) {
-        const size_t pad =
-            occupancy_pad(reinterpret_cast<const void *>(fwd_soa<d2, double>), SU3_WAVES_SOA_F64, kSoaBlock, pad64);
-        return launch_k(fwd_soa<d2, double>, grid, dim3(kSoaBlock), s, pad, (const d2 *)a, (const double *)b, (d2 *)c,
-                        sites, pitch, nbp, xcd);
+    if (elem_bytes == 16)
+        return launch_soa<d2, double, 1>(a, b, c, sites, pitch, SU3_WAVES_SOA_F64, s);
+    switch (soa_phases(sites, pitch, elem_bytes)) {
+    case 1: return launch_soa<f2, float, 1>(a, b, c, sites, pitch, SU3_WAVES_SOA_F32, s);
+    case 2: return launch_soa<f2, float, 2>(a, b, c, sites, pitch, SU3_WAVES_SOA_F32, s);
+    default: return launch_soa<f2, float, 3>(a, b, c, sites, pitch, SU3_WAVES_SOA_F32, s);
     }
-    const size_t pad =
-        occupancy_pad(reinterpret_cast<const void *>(fwd_soa<f2, float>), SU3_WAVES_SOA_F32, kSoaBlock, pad32);
-    return launch_k(fwd_soa<f2, float>, grid, dim3(kSoaBlock), s, pad, (const f2 *)a, (const float *)b, (f2 *)c, sites,
-                    pitch, nbp, xcd);
 }
 
 } // namespace su3

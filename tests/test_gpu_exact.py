@@ -284,3 +284,29 @@ def test_soa_pitched_exact(ops):
                 sa = ops.aos_to_soa(ta.to(dt), pitch)
                 sc = ops.mult_nn_soa(sa, tb.to(dt), sites=sites)
                 assert _same(ops.soa_to_aos(sc, sites), want)
+
+
+def test_soa_f32_load_phases_exact(ops):
+    """The FP32 SoA product on the dense layout issues its three plane loads
+    in two phases, or in three where the plane stride (8 B x sites) lies
+    within 128 KiB of a multiple of 8 MiB and is at least 16 MiB. Site counts
+    that take each count (999 and 2^20: two; 2^21 + 37 and 3 * 2^20 + 5000:
+    three; ragged ones among them), and the padded layout (one phase), must
+    equal integer arithmetic bit for bit. The expected products are torch's
+    complex128 products on the GPU, exact for these integer entries."""
+    rng = np.random.default_rng(919191)
+    for sites, phases in ((999, 2), (2 ** 20, 2), (2 ** 21 + 37, 3), (3 * 2 ** 20 + 5000, 3)):
+        m8 = (8 * sites) % (8 << 20)
+        on8 = m8 < (128 << 10) or m8 > (8 << 20) - (128 << 10)
+        assert phases == (3 if on8 and 8 * sites >= (16 << 20) - (128 << 10) else 2)
+        say("exact SoA FP32 load phases sites=%d phases=%d" % (sites, phases))
+        a = to_dev(_ints(rng, (sites, 4, 3, 3)))
+        b = to_dev(_ints(rng, (4, 3, 3)))
+        want = torch.matmul(a, b)
+        a32, b32 = a.to(torch.complex64), b.to(torch.complex64)
+        got = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a32), b32))
+        assert torch.equal(torch.view_as_real(got.to(torch.complex128)), torch.view_as_real(want))
+        pitch = ops.soa_pitch(sites, ops.SU3_F32)
+        got = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a32, pitch), b32, sites=sites), sites)
+        assert torch.equal(torch.view_as_real(got.to(torch.complex128)), torch.view_as_real(want))
+        del a, a32, want, got

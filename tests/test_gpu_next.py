@@ -184,11 +184,11 @@ def test_mat_vec_l48_full(O, ops):
 def test_l48_products_full(O, ops):
     """L=48 (5,308,416 sites), the inputs and launch configuration the
     benchmark times: a b^H, a^H b, reconstruct-12 in and out, reconstruct-12
-    in FP64, the SoA product (dense and at the padded pitch), and the FP64
-    product on one GPU's share of the lattice split over 8 GPUs (the first
-    663,552 sites). Every output is written into a NaN-poisoned buffer (with
-    guard sites where the layout is site-major) and compared with the
-    oracle."""
+    in FP64, the SoA product (FP64 and FP32, dense and at the padded pitch),
+    and the FP64 product on one GPU's share of the lattice split over 8 GPUs
+    (the first 663,552 sites). Every output is written into a NaN-poisoned
+    buffer (with guard sites where the layout is site-major) and compared
+    with the oracle."""
     sites = L48
     a, b, ref = l48_case()
     ta, tb = to_dev(a), to_dev(b)
@@ -238,6 +238,22 @@ def test_l48_products_full(O, ops):
     got = ops.soa_to_aos(sc, sites).cpu().numpy()
     del sc
     assert O.max_abs_diff(got, ref) <= 1e-13
+    # FP32 SoA (the dense layout loads its planes in two phases at this
+    # stride; the padded one in one), every output against the FP64 oracle on
+    # the unrounded inputs at the FP32 tolerance
+    t32, b32 = ta.to(torch.complex64), tb.to(torch.complex64)
+    for pitch in (sites, ops.soa_pitch(sites, ops.SU3_F32)):
+        say("L=48 SoA FP32, pitch %d" % pitch)
+        sa = ops.aos_to_soa(t32, pitch)
+        sc = poison_(torch.empty_like(sa))
+        ops.mult_nn_soa(sa, b32, out=sc, sites=sites)
+        del sa
+        if pitch > sites:
+            assert bool(torch.isnan(torch.view_as_real(sc[..., sites:])).all())
+        got = ops.soa_to_aos(sc, sites).cpu().numpy()
+        del sc
+        assert O.max_abs_diff(got.astype(np.complex128), ref) <= 5e-6
+    del t32
     say("L=48 / 8 share")
     ns = sites // 8
     got = run(lambda o: ops.mult_nn(ta[:ns], tb, out=o), (ns, 4, 3, 3), torch.complex128)
