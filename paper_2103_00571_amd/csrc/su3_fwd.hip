@@ -14,8 +14,10 @@
 //    uniform over a workgroup, so b[j] sits in scalar registers (fwd_soa).
 //  * The grid covers the lattice once: each wavefront streams one tile and
 //    exits. In the site-major kernels each XCD takes one contiguous eighth of
-//    the tiles (xcd_tile); the SoA kernel picks its order from the plane
-//    stride (soa_xcd).
+//    the tiles (xcd_tile); the SoA kernel picks its order (soa_xcd) and, in
+//    FP32, how many phases its plane loads take (soa_phases) from the plane
+//    stride, and takes any plane pitch >= the site count (soa_pitch gives
+//    the one that keeps the planes from colliding in HBM).
 //  * a and c are streamed with nontemporal 16-byte loads and stores.
 //  * 64-bit offsets throughout (a FP64 L=48 lattice is 3.06e9 bytes).
 #include "su3_internal.hpp"
@@ -570,7 +572,8 @@ static int soa_phases(int64_t sites, int64_t pitch, int elem_bytes)
 // at 14 site counts from 24^4 to 56^4 (powers of two and their neighbours
 // among them), as the SoA rate over the site-major rate: 0.976-1.031 (mean
 // 0.996) in FP64 and 0.972-1.020 (mean 0.994) in FP32, where the dense layout
-// ran at 0.934-1.020 (0.981) and 0.845-1.024 (0.957). The pad is not monotone
+// ran at 0.934-1.020 (0.981) and, before the FP32 load phases, 0.845-1.024
+// (0.957); with them 0.909-1.052 (0.989) in another run. The pad is not monotone
 // in its effect, and no fixed residue of the plane stride mod 64 KiB did as
 // well at every size: a 1 KiB FP64 stride residue left 2^20 - 64 at 0.89,
 // and 16 KiB left 2^20 at 0.86.
