@@ -15,7 +15,7 @@
 //  * The grid covers the lattice once: each wavefront streams one tile and
 //    exits. In the site-major kernels each XCD takes one contiguous eighth of
 //    the tiles (xcd_tile); the SoA kernel picks its order (soa_xcd) and, in
-//    FP32, how many phases its plane loads take (soa_phases) from the plane
+//    how many phases its plane loads take (soa_waits) from the plane
 //    stride, and takes any plane pitch >= the site count (soa_pitch gives
 //    the one that keeps the planes from colliding in HBM).
 //  * a and c are streamed with nontemporal 16-byte loads and stores.
@@ -60,6 +60,10 @@
 #endif
 #ifndef SU3_WAVES_SOA_F32
 #define SU3_WAVES_SOA_F32 0
+#endif
+// FP64 SoA with its plane loads in two phases (soa_waits)
+#ifndef SU3_WAVES_SOA_F64_PHASED
+#define SU3_WAVES_SOA_F64_PHASED 16
 #endif
 
 namespace su3 {
@@ -480,13 +484,13 @@ __global__ __launch_bounds__(kAosBlock) void fwd_aos(const u4 *__restrict__ a, c
 // which gives each XCD one contiguous eighth of the row's site blocks (nbp
 // is then the row's block count rounded up to a multiple of 8, so that
 // `local` mod 8 is the XCD; the extra workgroups find no sites and exit).
-// kPhases splits a thread's three plane loads into phases (soa_phases): 1
-// issues them together; 2 issues planes 0 and 1, then waits for them before
-// it issues plane 2; 3 waits after every plane. A wait is an empty asm
-// statement that takes the accumulators as inputs, so every load before it
-// has completed and no later load moves above it. The arithmetic and its
-// order are the same in every phase count, so the output is bit-identical.
-template <typename V, typename S, int kPhases>
+// kWaits splits a thread's three plane loads into phases (soa_waits): bit 0
+// waits for plane 0 before plane 1 is loaded, bit 1 waits for planes 0 and 1
+// before plane 2 is loaded; 0 issues all three together. A wait is an empty
+// asm statement that takes the accumulators as inputs, so every load before
+// it has completed and no later load moves above it. The arithmetic and its
+// order are the same for every kWaits, so the output is bit-identical.
+template <typename V, typename S, int kWaits>
 __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, const S *__restrict__ b,
                                                   V *__restrict__ c, int64_t n, int64_t pitch, int64_t nbp, int xcd)
 {
@@ -512,7 +516,7 @@ __global__ __launch_bounds__(kSoaBlock) void fwd_soa(const V *__restrict__ a, co
 #pragma unroll
         for (int l = 0; l < 3; ++l)
             cmac(re[l], im[l], x.x, x.y, br[3 * m + l], bi[3 * m + l]);
-        if ((kPhases == 3 && m < 2) || (kPhases == 2 && m == 1))
+        if ((kWaits >> m) & 1)
             asm volatile("" ::"v"(re[0]), "v"(im[0]), "v"(re[1]), "v"(im[1]), "v"(re[2]), "v"(im[2]) : "memory");
     }
 #pragma unroll
@@ -548,22 +552,38 @@ static bool soa_xcd(int64_t sites, int64_t pitch, int elem_bytes)
 // workgroup's planes arrive one after another, so at any moment the
 // resident workgroups, which started at different times, read different
 // planes at different site offsets. That costs bytes in flight per
-// wavefront. FP32 (no occupancy cap) gains, measured on random data at 16 site
-// counts from 24^4 to 56^4. Stock kernel: 0.84-1.05 of the site-major rate
-// (mean 0.954). Two phases: 0.88-1.04 (0.981). Three phases are best where
-// the plane stride is a multiple of 8 MiB and at least 16 MiB: 0.92-0.98
-// there, against 0.84-0.95 for the stock kernel and 0.88-0.98 for two
-// phases. FP64 keeps one phase: with its occupancy cap of 8 wavefronts the
-// phased kernel lost up to a third, and with caps of 16 or 24 it was 1-2%
-// slower on average. The padded layout keeps one phase too: its stride does
-// not collide.
-static int soa_phases(int64_t sites, int64_t pitch, int elem_bytes)
+// wavefront, which more resident wavefronts make up for.
+// FP32 (no occupancy cap), measured on random data at 16 site counts from
+// 24^4 to 56^4 as the rate over site-major. Stock kernel: 0.84-1.05 (mean
+// 0.954). Waiting before plane 2: 0.88-1.04 (0.981). Waiting after every
+// plane is best where the plane stride is a multiple of 8 MiB and at least
+// 16 MiB: 0.92-0.98 there, against 0.84-0.95 stock and 0.88-0.98 with one
+// wait.
+// FP64 loses with waits at its occupancy cap of 8 wavefronts (up to a
+// third), and with a cap of 16 it is 1-2% slower on average, but at
+// plane strides that are multiples of 16 MiB one wait after plane 0 with a
+// cap of 16 gained: 0.996-1.013 against 0.960-0.966 at 16 MiB (L=32),
+// 0.963 against 0.955 at 48 MiB, 0.944 against 0.935 at 128 MiB, and
+// 0.95-0.96 either way at 32 and 64 MiB.
+// The padded layout keeps no waits: its stride does not collide.
+// Returns the wait mask; *waves is the occupancy cap to launch with.
+static int soa_waits(int64_t sites, int64_t pitch, int elem_bytes, int *waves)
 {
-    if (elem_bytes != 8 || pitch != sites)
-        return 1;
-    const int64_t stride = sites * 8, m8 = stride % ((int64_t)8 << 20);
-    const bool on8 = m8 < ((int64_t)128 << 10) || m8 > ((int64_t)8 << 20) - ((int64_t)128 << 10);
-    return on8 && stride >= ((int64_t)16 << 20) - ((int64_t)128 << 10) ? 3 : 2;
+    const int64_t stride = sites * elem_bytes;
+    auto near = [stride](int64_t period) {
+        const int64_t m = stride % period;
+        return m < ((int64_t)128 << 10) || m > period - ((int64_t)128 << 10);
+    };
+    const int64_t lo16 = ((int64_t)16 << 20) - ((int64_t)128 << 10);
+    if (elem_bytes == 16) {
+        const bool phased = pitch == sites && stride >= lo16 && near((int64_t)16 << 20);
+        *waves = phased ? SU3_WAVES_SOA_F64_PHASED : SU3_WAVES_SOA_F64;
+        return phased ? 1 : 0;
+    }
+    *waves = SU3_WAVES_SOA_F32;
+    if (pitch != sites)
+        return 0;
+    return near((int64_t)8 << 20) && stride >= lo16 ? 3 : 2;
 }
 
 // Plane pitch of the padded SoA layout at which the product streams at the
@@ -692,7 +712,7 @@ hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, i
     return launch_aos<FormAnF32>(a, b, c, sites, s);
 }
 
-template <typename V, typename S, int kPhases>
+template <typename V, typename S, int kWaits>
 static hipError_t launch_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int waves,
                              hipStream_t s)
 {
@@ -701,20 +721,23 @@ static hipError_t launch_soa(const void *a, const void *b, void *c, int64_t site
     const int64_t nbp = soa_blocks_per_row(sites, pitch, es);
     const int xcd = soa_xcd(sites, pitch, es) ? 1 : 0;
     const size_t pad =
-        occupancy_pad(reinterpret_cast<const void *>(fwd_soa<V, S, kPhases>), waves, kSoaBlock, pad_cache);
-    return launch_k(fwd_soa<V, S, kPhases>, dim3((unsigned)(12 * nbp)), dim3(kSoaBlock), s, pad, (const V *)a,
+        occupancy_pad(reinterpret_cast<const void *>(fwd_soa<V, S, kWaits>), waves, kSoaBlock, pad_cache);
+    return launch_k(fwd_soa<V, S, kWaits>, dim3((unsigned)(12 * nbp)), dim3(kSoaBlock), s, pad, (const V *)a,
                     (const S *)b, (V *)c, sites, pitch, nbp, xcd);
 }
 
 hipError_t launch_fwd_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int elem_bytes,
                           hipStream_t s)
 {
+    int waves = 0;
+    const int waits = soa_waits(sites, pitch, elem_bytes, &waves);
     if (elem_bytes == 16)
-        return launch_soa<d2, double, 1>(a, b, c, sites, pitch, SU3_WAVES_SOA_F64, s);
-    switch (soa_phases(sites, pitch, elem_bytes)) {
-    case 1: return launch_soa<f2, float, 1>(a, b, c, sites, pitch, SU3_WAVES_SOA_F32, s);
-    case 2: return launch_soa<f2, float, 2>(a, b, c, sites, pitch, SU3_WAVES_SOA_F32, s);
-    default: return launch_soa<f2, float, 3>(a, b, c, sites, pitch, SU3_WAVES_SOA_F32, s);
+        return waits ? launch_soa<d2, double, 1>(a, b, c, sites, pitch, waves, s)
+                     : launch_soa<d2, double, 0>(a, b, c, sites, pitch, waves, s);
+    switch (waits) {
+    case 0: return launch_soa<f2, float, 0>(a, b, c, sites, pitch, waves, s);
+    case 2: return launch_soa<f2, float, 2>(a, b, c, sites, pitch, waves, s);
+    default: return launch_soa<f2, float, 3>(a, b, c, sites, pitch, waves, s);
     }
 }
 

@@ -286,27 +286,42 @@ def test_soa_pitched_exact(ops):
                 assert _same(ops.soa_to_aos(sc, sites), want)
 
 
-def test_soa_f32_load_phases_exact(ops):
-    """The FP32 SoA product on the dense layout issues its three plane loads
-    in two phases, or in three where the plane stride (8 B x sites) lies
-    within 128 KiB of a multiple of 8 MiB and is at least 16 MiB. Site counts
-    that take each count (999 and 2^20: two; 2^21 + 37 and 3 * 2^20 + 5000:
-    three; ragged ones among them), and the padded layout (one phase), must
-    equal integer arithmetic bit for bit. The expected products are torch's
-    complex128 products on the GPU, exact for these integer entries."""
+def test_soa_load_phases_exact(ops):
+    """The SoA product on the dense layout splits each thread's three plane
+    loads into phases, from the plane stride S: FP32 waits before plane 2,
+    and after every plane where S lies within 128 KiB of a multiple of 8 MiB
+    and is at least 16 MiB; FP64 waits after plane 0 where S lies within
+    128 KiB of a multiple of 16 MiB (and is at least 16 MiB), else not at
+    all. Site counts that take each choice, ragged ones among them, and the
+    padded layout (no waits), must equal integer arithmetic bit for bit. The
+    expected products are torch's complex128 products on the GPU, exact for
+    these integer entries."""
     rng = np.random.default_rng(919191)
-    for sites, phases in ((999, 2), (2 ** 20, 2), (2 ** 21 + 37, 3), (3 * 2 ** 20 + 5000, 3)):
-        m8 = (8 * sites) % (8 << 20)
-        on8 = m8 < (128 << 10) or m8 > (8 << 20) - (128 << 10)
-        assert phases == (3 if on8 and 8 * sites >= (16 << 20) - (128 << 10) else 2)
-        say("exact SoA FP32 load phases sites=%d phases=%d" % (sites, phases))
+
+    def near(stride, period):
+        m = stride % period
+        return m < (128 << 10) or m > period - (128 << 10)
+
+    lo16 = (16 << 20) - (128 << 10)
+    cases = ((ops.SU3_F32, 999, 1), (ops.SU3_F32, 2 ** 20, 1), (ops.SU3_F32, 2 ** 21 + 37, 2),
+             (ops.SU3_F32, 3 * 2 ** 20 + 5000, 2), (ops.SU3_F64, 999, 0), (ops.SU3_F64, 2 ** 19, 0),
+             (ops.SU3_F64, 2 ** 20, 1), (ops.SU3_F64, 2 ** 20 + 37, 1), (ops.SU3_F64, 3 * 2 ** 20 - 3000, 1))
+    for form, sites, waits in cases:
+        es = 16 if form == ops.SU3_F64 else 8
+        stride = es * sites
+        if form == ops.SU3_F64:
+            assert waits == (1 if stride >= lo16 and near(stride, 16 << 20) else 0)
+        else:
+            assert waits == (2 if near(stride, 8 << 20) and stride >= lo16 else 1)
+        say("exact SoA load phases form=%d sites=%d waits=%d" % (form, sites, waits))
         a = to_dev(_ints(rng, (sites, 4, 3, 3)))
         b = to_dev(_ints(rng, (4, 3, 3)))
         want = torch.matmul(a, b)
-        a32, b32 = a.to(torch.complex64), b.to(torch.complex64)
-        got = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a32), b32))
+        dt = torch.complex128 if form == ops.SU3_F64 else torch.complex64
+        ax, bx = a.to(dt), b.to(dt)
+        got = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(ax), bx))
         assert torch.equal(torch.view_as_real(got.to(torch.complex128)), torch.view_as_real(want))
-        pitch = ops.soa_pitch(sites, ops.SU3_F32)
-        got = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a32, pitch), b32, sites=sites), sites)
+        pitch = ops.soa_pitch(sites, form)
+        got = ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(ax, pitch), bx, sites=sites), sites)
         assert torch.equal(torch.view_as_real(got.to(torch.complex128)), torch.view_as_real(want))
-        del a, a32, want, got
+        del a, ax, want, got
