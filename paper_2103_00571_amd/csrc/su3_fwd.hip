@@ -712,6 +712,8 @@ hipError_t launch_fwd_an(const void *a, const void *b, void *c, int64_t sites, i
     return launch_aos<FormAnF32>(a, b, c, sites, s);
 }
 
+// Each instantiation is launched with one occupancy cap only (soa_waits maps
+// the wait mask to its cap), so one pad cache per instantiation suffices.
 template <typename V, typename S, int kWaits>
 static hipError_t launch_soa(const void *a, const void *b, void *c, int64_t sites, int64_t pitch, int waves,
                              hipStream_t s)
