@@ -30,18 +30,78 @@ typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 // major side is read or written as one contiguous run of 64*36 elements, the
 // plane side as 36 contiguous runs of 64 elements. The LDS row has one
 // element of padding so that the column walk does not hit one bank.
+// A whole tile is moved with every load of a thread issued before the first
+// LDS write (9 elements per thread), nontemporal loads and stores, and, in
+// FP64, the XCD-contiguous tile order (each XCD one contiguous eighth of the
+// tiles; a one-pass grid). Against element-at-a-time loops with plain
+// accesses in tile = workgroup index order (random data, AoS -> SoA / SoA ->
+// AoS, TB/s): FP64 L=48 5.30 / 5.75 against 5.31 / 5.62, L=32 5.65 / 5.85
+// against 5.16 / 5.47; FP32 (workgroup order: the XCD order was 0-6% slower
+// there) L=48 5.64 / 5.96 against 5.33 / 5.54, L=32 6.06 / 5.80 against
+// 5.04 / 5.15. 128- and 64-thread workgroups, 32-site tiles and loads in
+// three phases were within 2% either way or slower. The last, ragged tile
+// moves element by element.
 constexpr int kTileSites = 64;
 
-template <typename V, bool kToSoa>
+template <typename V, bool kToSoa, bool kXcd>
 __global__ __launch_bounds__(kBlock) void transpose_aos_soa(const V *__restrict__ src, V *__restrict__ dst,
                                                             int64_t n, int64_t pitch)
 {
     __shared__ V tile[36][kTileSites + 1];
+    constexpr int kPer = 36 * kTileSites / kBlock;
+    static_assert(kPer * kBlock == 36 * kTileSites, "a tile splits evenly over the workgroup");
     const int64_t tiles = (n + kTileSites - 1) / kTileSites;
-    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    // the XCD order needs the one-pass grid (one workgroup per tile)
+    int64_t t = blockIdx.x;
+    if (kXcd && (int64_t)gridDim.x >= tiles)
+        t = xcd_order(blockIdx.x, gridDim.x);
+    for (; t < tiles; t += gridDim.x) {
         const int64_t s0 = t * kTileSites;
         const int ns = (int)((n - s0) < kTileSites ? (n - s0) : kTileSites);
-        if (kToSoa) {
+        if (ns == kTileSites) {
+            V v[kPer];
+            if (kToSoa) {
+#pragma unroll
+                for (int i = 0; i < kPer; ++i)
+                    v[i] = ld_stream(src + s0 * 36 + threadIdx.x + i * kBlock);
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int e = threadIdx.x + i * kBlock;
+                    tile[e % 36][e / 36] = v[i];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int e = threadIdx.x + i * kBlock;
+                    v[i] = tile[e / kTileSites][e % kTileSites];
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int e = threadIdx.x + i * kBlock;
+                    st_stream(dst + (int64_t)(e / kTileSites) * pitch + s0 + e % kTileSites, v[i]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int e = threadIdx.x + i * kBlock;
+                    v[i] = ld_stream(src + (int64_t)(e / kTileSites) * pitch + s0 + e % kTileSites);
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int e = threadIdx.x + i * kBlock;
+                    tile[e / kTileSites][e % kTileSites] = v[i];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int e = threadIdx.x + i * kBlock;
+                    v[i] = tile[e % 36][e / 36];
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i)
+                    st_stream(dst + s0 * 36 + threadIdx.x + i * kBlock, v[i]);
+            }
+        } else if (kToSoa) {
             for (int e = threadIdx.x; e < ns * 36; e += kBlock)
                 tile[e % 36][e / 36] = src[s0 * 36 + e];
             __syncthreads();
@@ -298,16 +358,16 @@ hipError_t launch_aos_soa(const void *src, void *dst, int64_t sites, int64_t pit
     const unsigned g = grid_for(sites, kTileSites);
     if (elem_bytes == 16) {
         if (to_soa)
-            return launch_k(transpose_aos_soa<d2, true>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites,
-                            pitch);
-        return launch_k(transpose_aos_soa<d2, false>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst, sites,
-                        pitch);
+            return launch_k(transpose_aos_soa<d2, true, true>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst,
+                            sites, pitch);
+        return launch_k(transpose_aos_soa<d2, false, true>, dim3(g), dim3(kBlock), s, 0, (const d2 *)src, (d2 *)dst,
+                        sites, pitch);
     }
     if (to_soa)
-        return launch_k(transpose_aos_soa<f2, true>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites,
-                        pitch);
-    return launch_k(transpose_aos_soa<f2, false>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst, sites,
-                    pitch);
+        return launch_k(transpose_aos_soa<f2, true, false>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst,
+                        sites, pitch);
+    return launch_k(transpose_aos_soa<f2, false, false>, dim3(g), dim3(kBlock), s, 0, (const f2 *)src, (f2 *)dst,
+                    sites, pitch);
 }
 
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
