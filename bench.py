@@ -220,6 +220,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=1,
+                    help="seed of a; b, dC and the colour vectors take seed+1, seed+2, seed+3")
     ap.add_argument("--forms",
                     default="f64,shard8,l32,soa,soap,f32,bf16,r12,r12c,r12f64,na,an,matvec,fp32more,setup,copy,shapes,bwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -250,8 +252,8 @@ def main() -> int:
     sites = L ** 4
 
     t0 = time.perf_counter()
-    a = latgen.random_lattice(sites, seed=1)
-    b = latgen.random_b(seed=2)
+    a = latgen.random_lattice(sites, seed=args.seed)
+    b = latgen.random_b(seed=args.seed + 1)
     log("generated L=%d lattice (%d sites, %.2f GB) in %.1f s" % (L, sites, a.nbytes / 1e9, time.perf_counter() - t0))
     ta = torch.from_numpy(a).to(dev)
     tb64 = torch.from_numpy(b).to(dev)
@@ -444,7 +446,7 @@ def main() -> int:
             record(name, ms, BYTES_PER_SITE[name], sites)
             del y
     if "matvec" in forms:
-        tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=4)[:, 0, 0, :].copy()).to(dev)
+        tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=args.seed + 3)[:, 0, 0, :].copy()).to(dev)
         w = ops.mat_vec(ta, tv)
         ms = time_launches(lambda: ops.mat_vec(ta, tv, out=w), args.steps, args.warmup, torch, LEG_WARM_S)
         record("matvec", ms, BYTES_PER_SITE["matvec"], sites)
@@ -500,7 +502,7 @@ def main() -> int:
             record(name, time_launches(lambda: fn(t32, tb32, out=y), args.steps, args.warmup, torch, LEG_WARM_S),
                    BYTES_PER_SITE[name], sites)
         del y
-        tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=4)[:, 0, 0, :].copy()).to(dev)
+        tv = torch.from_numpy(latgen.complex_normal_lattice(sites, seed=args.seed + 3)[:, 0, 0, :].copy()).to(dev)
         tv = tv.to(torch.complex64)
         w = ops.mat_vec(t32, tv)
         record("matvec32", time_launches(lambda: ops.mat_vec(t32, tv, out=w), args.steps, args.warmup, torch, LEG_WARM_S),
@@ -524,7 +526,7 @@ def main() -> int:
         bs = args.bwd_L ** 4
         xa = torch.from_numpy(np.ascontiguousarray(a[:bs])).to(dev) if bs <= sites else None
         if xa is not None:
-            xdc = torch.from_numpy(latgen.complex_normal_lattice(bs, seed=3)).to(dev)
+            xdc = torch.from_numpy(latgen.complex_normal_lattice(bs, seed=args.seed + 2)).to(dev)
             for name, dt, tb in (("bwd_f64", torch.complex128, tb64), ("bwd_f32", torch.complex64, tb32)):
                 xa_, xdc_ = xa.to(dt), xdc.to(dt)
                 # preallocated outputs and workspace, as in the forward legs
@@ -601,7 +603,7 @@ def main() -> int:
         "data": "synthetic (seeded Haar SU(3) links, SplitMix64 + Box-Muller)",
         "config": {"workload": "su3_mult_nn FP64 AoS, L=%d (%d sites, 4 links/site)" % (L, sites),
                    "L": L, "sites": sites, "layout": "aos", "precision": "f64",
-                   "bytes_per_site": BYTES_PER_SITE["f64"], "flop_per_site": FLOP_PER_SITE},
+                   "bytes_per_site": BYTES_PER_SITE["f64"], "flop_per_site": FLOP_PER_SITE, "seed": args.seed},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": results,
