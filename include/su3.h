@@ -162,8 +162,12 @@ int su3_mult_nn_soa(const void *a, const void *b, void *c, int64_t sites,
  * su3_mult_nn_soa. In the dense layout the three planes a row reads lie one
  * plane stride apart, and at some site counts (powers of two among them) the
  * same offsets of those planes collide in HBM; a padded stride avoids that,
- * the way lattice QCD codes pad their field strides. su3_soa_pitch gives the
- * pitch at which the product streams at the site-major rate. Arguments,
+ * the way lattice QCD codes pad their field strides. When the site count is
+ * not a multiple of 8 (SU3_F64) or 16 (SU3_F32), dense planes also start off
+ * 128-byte boundaries, and their partial-line writes cost the product and the
+ * AoS -> SoA transform 10-25%; a pitch that is a multiple of 64 sites keeps
+ * every plane aligned. su3_soa_pitch gives the pitch at which the product
+ * streams at the site-major rate. Arguments,
  * alignment and errors as su3_mult_nn_soa; a and c each span 36*pitch
  * complex elements, c must not overlap a or b; pitch < sites returns
  * SU3_ERR_SIZE.
