@@ -250,3 +250,28 @@ def test_torch_front_end_rejects_cpu_and_bad_shapes():
         ops.form_of(torch.zeros((3, 4, 3, 2), dtype=torch.complex128))
     assert ops.form_of(torch.zeros((3, 4, 2, 3), dtype=torch.complex64)) == ops.SU3_R12_F32
     assert ops.form_of(torch.zeros((3, 4, 3, 3, 2), dtype=torch.bfloat16)) == ops.SU3_BF16
+
+
+def test_torch_front_end_soa_arguments():
+    """The padded-SoA arguments of the torch front end are checked before any
+    allocation on, or call to, the GPU."""
+    import torch
+    from paper_2103_00571_amd import ops
+    x = torch.zeros((10, 4, 3, 3), dtype=torch.complex128)
+    s = torch.zeros((4, 3, 3, 16), dtype=torch.complex128)
+    b = torch.zeros((4, 3, 3), dtype=torch.complex128)
+    with pytest.raises(ValueError, match="pitch"):
+        ops.aos_to_soa(x, pitch=9)               # pitch below the site count
+    with pytest.raises(ValueError, match="sites"):
+        ops.soa_to_aos(s, sites=17)              # more sites than the pitch holds
+    with pytest.raises(ValueError, match="sites"):
+        ops.soa_to_aos(s, sites=-1)
+    with pytest.raises(ValueError, match="sites"):
+        ops.mult_nn_soa(s, b, sites=17)
+    with pytest.raises(ValueError):
+        ops.mult_nn_soa(s, b, sites=10)          # CPU tensors: never computed on the host
+    with pytest.raises(ValueError):
+        ops.mult_nn_soa(s, b.to(torch.complex64), sites=10)
+    with pytest.raises(ValueError):
+        ops.mult_nn_soa(s, b, out=torch.zeros((4, 3, 3, 15), dtype=torch.complex128), sites=10)
+    assert ops.soa_pitch(10, ops.SU3_F64) == 576 and ops.soa_pitch(10, ops.SU3_F32) == 192
