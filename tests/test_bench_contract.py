@@ -43,8 +43,8 @@ def test_kernel_hash_ignores_comments_and_layout_only():
 def test_one_json_line_with_the_contract_keys():
     print("[gpu] bench.py short run", flush=True)
     proc = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1", "--L",
-                           "16", "--bwd-L", "8", "--forms", "f64,copy,shapes,bwd", "--cpu-seconds", "0.5",
-                           "--cpu-omp-seconds", "0.5"],
+                           "16", "--bwd-L", "8", "--forms", "f64,soa,soap,copy,shapes,bwd", "--cpu-seconds", "0.5",
+                           "--cpu-omp-seconds", "0.5", "--seed", "7"],
                           capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert proc.returncode == 0, proc.stderr[-2000:]
     lines = [l for l in proc.stdout.splitlines() if l.strip()]
@@ -65,3 +65,9 @@ def test_one_json_line_with_the_contract_keys():
     omp = c["openmp_all_cores"]
     assert omp["check_ok"] is True and omp["threads"] >= 1 and omp["value"] > 0
     assert omp["omp_proc_bind"] == "close" and omp["omp_places"] == "cores"
+    assert d["config"]["seed"] == 7
+    f = d["forms"]
+    assert f["soa"]["vs_site_major"] > 0 and f["soap"]["vs_site_major"] > 0
+    assert f["soap"]["pitch"] == (16 ** 4 + 63) // 64 * 64 + 512      # su3_soa_pitch, FP64
+    for name in ("soa", "soap"):
+        assert f[name]["max_abs_err_vs_oracle"] <= 1e-13
