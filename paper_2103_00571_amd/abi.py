@@ -12,7 +12,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsu3.so")
+# SU3_LIB_PATH selects another build of the same library (a sanitized one in
+# the tests); by default the in-tree libsu3.so.
+LIB_PATH = os.environ.get("SU3_LIB_PATH") or os.path.join(_HERE, "libsu3.so")
 
 # su3.h constants
 ABI_VERSION = 6

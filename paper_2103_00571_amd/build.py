@@ -40,9 +40,12 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(output: str = LIB, defines: list[str] | None = None, verbose: bool = False) -> str:
-    """Compile the library; returns the output path. Raises on failure."""
-    cmd = [HIPCC, *FLAGS, *("-D" + d for d in (defines or [])), *sources(), "-o", output + ".tmp"]
+def build(output: str = LIB, defines: list[str] | None = None, verbose: bool = False,
+          extra: list[str] | None = None) -> str:
+    """Compile the library; returns the output path. Raises on failure.
+    `extra` holds further hipcc flags (the sanitizer test passes host-only
+    sanitizer flags here)."""
+    cmd = [HIPCC, *FLAGS, *(extra or []), *("-D" + d for d in (defines or [])), *sources(), "-o", output + ".tmp"]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 target feature and says
     # so; that line is expected and dropped.
