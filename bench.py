@@ -1,6 +1,6 @@
 """Benchmark of the SU(3) link multiply c[s][j] = a[s][j] b[j] on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--L 48] [--forms f64,shard8,soa,...,copy,bwd]
+    python bench.py [--steps K | -I K] [--warmup W | -W W] [--L 48] [--seed S] [--forms f64,shard8,soa,...,copy,bwd]
 
 One step is one pass of the product over the whole lattice. The headline is
 the FP64 site-major (AoS) product on an L=48 lattice (5,308,416 sites, 3.06 GB
@@ -216,8 +216,9 @@ def cpu_omp_leg(sites: int, seconds: float) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=20)
+    # -I and -W are SU3_Bench's own names for the timed and warm-up iterations
+    ap.add_argument("--steps", "-I", type=int, default=100)
+    ap.add_argument("--warmup", "-W", type=int, default=20)
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--bwd-L", type=int, default=32)
     ap.add_argument("--seed", type=int, default=1,
