@@ -32,11 +32,18 @@ def test_host_threads_on_separate_streams(ops):
     dc = to_dev(latgen.complex_normal_lattice(sites, seed=83))
     b32 = b.to(torch.complex64)
     packed = {code: ops.pack(a, code) for code in (ops.SU3_F32, ops.SU3_BF16, ops.SU3_R12_F32)}
+    a32 = packed[ops.SU3_F32]
+    pitch = ops.soa_pitch(sites, ops.SU3_F64)
     torch.cuda.synchronize()
 
     def work():
         outs = [ops.mult_nn(a, b), ops.mult_na(a, b), ops.mult_an(a, b)]
         outs += [ops.mult_nn(x, b32) for x in packed.values()]
+        # SoA: both precisions on the dense layout, FP64 on the padded one,
+        # through the transforms each way
+        outs += [ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a), b)),
+                 ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a32), b32)),
+                 ops.soa_to_aos(ops.mult_nn_soa(ops.aos_to_soa(a, pitch), b, sites=sites), sites)]
         da, db = ops.mult_nn_bwd(a, b, dc)
         return outs + [da, db]
 

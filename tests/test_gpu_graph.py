@@ -63,3 +63,54 @@ def test_forward_and_adjoint_replay(ops):
         torch.cuda.synchronize()
         for x, y in zip(got, (c, da, db)):
             assert torch.equal(torch.view_as_real(x), torch.view_as_real(y)), "replay %d differs" % rep
+
+
+def test_soa_replay(ops):
+    """The SoA product and the layout transforms under capture: the dense FP32
+    product (its loads in phases) and the padded FP64 product, each between
+    an AoS -> SoA and an SoA -> AoS transform."""
+    say("graph capture SoA")
+    from paper_2103_00571_amd import abi
+    sites = 2 ** 21 + 37          # FP32 dense: plane stride 16 MiB + 296 B, three load phases
+    a64 = to_dev(latgen.random_lattice(sites, seed=64))
+    a32 = a64.to(torch.complex64)
+    b64 = to_dev(latgen.random_b(seed=65))
+    b32 = b64.to(torch.complex64)
+    pitch = ops.soa_pitch(sites, ops.SU3_F64)
+    s32, t32 = (torch.empty(36 * sites, dtype=torch.complex64, device=a64.device) for _ in range(2))
+    s64, t64 = (torch.empty(36 * pitch, dtype=torch.complex128, device=a64.device) for _ in range(2))
+    c32, c64 = torch.empty_like(a32), torch.empty_like(a64)
+
+    def step(st):
+        F32, F64 = ops.SU3_F32, ops.SU3_F64
+        abi.check(abi.su3_aos_to_soa(a32.data_ptr(), s32.data_ptr(), sites, F32, st), "to soa 32")
+        abi.check(abi.su3_mult_nn_soa(s32.data_ptr(), b32.data_ptr(), t32.data_ptr(), sites, F32, st), "soa 32")
+        abi.check(abi.su3_soa_to_aos(t32.data_ptr(), c32.data_ptr(), sites, F32, st), "to aos 32")
+        abi.check(abi.su3_aos_to_soa_pitched(a64.data_ptr(), s64.data_ptr(), sites, pitch, F64, st), "to soa 64")
+        abi.check(abi.su3_mult_nn_soa_pitched(s64.data_ptr(), b64.data_ptr(), t64.data_ptr(), sites, pitch, F64, st),
+                  "soa 64")
+        abi.check(abi.su3_soa_to_aos_pitched(t64.data_ptr(), c64.data_ptr(), sites, pitch, F64, st), "to aos 64")
+
+    step(torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s):
+        step(s.cuda_stream)
+    torch.cuda.synchronize()
+
+    for rep in range(3):
+        a64.mul_(complex(np.cos(0.4 * rep), np.sin(0.4 * rep)))
+        a32.copy_(a64)
+        c32.fill_(float("nan"))
+        c64.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (c32.clone(), c64.clone())
+        step(torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        for x, y in zip(got, (c32, c64)):
+            assert torch.equal(torch.view_as_real(x), torch.view_as_real(y)), "replay %d differs" % rep
+        assert bool(torch.isfinite(torch.view_as_real(c64)).all()) and bool(torch.isfinite(torch.view_as_real(c32)).all())
